@@ -1,0 +1,260 @@
+#!/usr/bin/env python3
+"""Benchmark of the MPPI update on one MI355X.
+
+Default workload: the single-instance configuration (K = 4096 rollouts, N = 100
+steps of 10 ms, 20 spheres, straight-line reference at 12 m/s) run in closed loop:
+every step is one full MPPI update (rollouts, weights, weighted update, apply and
+shift) followed by one noise-free plant step on the device, with the applied control
+copied to the host and the host synchronised per update ("plain": one solve per
+launch sequence).  Inputs (references for every step, obstacles, warm start) are
+resident on the device before the timed region starts.
+
+Prints ONE JSON line on stdout (everything else goes to stderr):
+  value          rollout-steps/s = K * N * steps / wall time of the timed steps
+  latency_ms     p50 / p99 / mean host-side latency per update (launch -> u_0 on host)
+  roofline       the rollout kernel (dominant): algorithmic FP32 FLOP per launch over
+                 its average duration, measured with HIP events on its stream
+  reduction      weighted-sum kernel: algorithmic bytes over its duration (HBM)
+  cpu_baseline   the FP64 oracle on the host cores, on a bounded sample
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rollout-steps/s + p50/p99 MPPI update latency, batched/served vs plain, 1 GPU"
+PEAK_FP32_VECTOR = 157.3e12     # MI355X published FP32 vector peak (packed FMA)
+PEAK_FP32_UNPACKED = 78.6e12    # 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz (no packed FP32)
+PEAK_HBM = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Algorithmic work per unit (counted from the kernels' formulation; FMA = 2 FLOP,
+# each transcendental (log2, sqrt, sin, cos, rsqrt) = 1 FLOP)
+# ---------------------------------------------------------------------------
+
+FLOP_STEP_BASE = {
+    "noise": 22,          # 4 uniforms, 2 x (log, mul, sqrt), 4 x (trig, 2 mul)
+    "perturb": 4,         # u = u_nom + du
+    "input_cost": 28,     # u^T R u (12) and du^T R_d du (16)
+    "controller": 40,     # Eqs. (8)-(12): rates, torques, Gamma^-1, clip
+    "rk4": 516,           # 4 x 70 derivative + 221 stage combinations + 12 renorm + 3
+    "tracking": 44,       # Eq. (18) with Eq. (21)
+    "obstacle_epilogue": 2,
+    "accumulate": 5,      # Kahan add and the step sum
+}
+FLOP_PER_OBSTACLE = 11     # 2 sub, sub + mul (z mask), mul + 2 fma, 2 compares
+
+
+def flop_per_rollout_step(M: int) -> int:
+    return sum(FLOP_STEP_BASE.values()) + FLOP_PER_OBSTACLE * M
+
+
+def rollout_flop_per_launch(K: int, N: int, M: int) -> float:
+    # N steps plus the scoring of the initial state (tracking + obstacles)
+    return float(K) * (N * flop_per_rollout_step(M) + 44 + FLOP_PER_OBSTACLE * M + 2 + 5)
+
+
+def reduction_bytes_per_launch(K: int, N: int) -> float:
+    # delta_u [N][4][K] read once, weights [K] once, u_nom read and u_upd written
+    return 4.0 * (4 * K * N + K + 8 * N)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("model.h", "kernels.hip", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_2407_09812_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(K, N, M):
+    """HBM bytes per rollout launch from the committed rocprofv3 PMC summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "rollout_c2_pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("workload") != [K, N, M]:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on the host cores (bounded sample)
+# ---------------------------------------------------------------------------
+
+def cpu_baseline(sc, seconds: float):
+    import numpy as np
+    import oracle
+    x = sc.x0.copy()
+    u_nom = sc.u_nom0()
+    n, t0 = 0, time.perf_counter()
+    while True:
+        r = oracle.update(sc.veh, sc.cost, sc.solve(n), x, u_nom, sc.x_ref(n), sc.obstacles)
+        x = oracle.model_step(sc.veh, x, r["u_apply"][:4], sc.dt)
+        u_nom = r["u_nom"]
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or n >= sc.updates:
+            break
+    return {"value": sc.K * sc.N * n / el, "unit": "rollout-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n} closed-loop FP64 updates of {sc.name} (K={sc.K}, N={sc.N}, M={sc.M}) "
+                      f"in {el:.1f} s"}
+
+
+# ---------------------------------------------------------------------------
+
+def percentile(v, q):
+    v = sorted(v)
+    if not v:
+        return float("nan")
+    i = min(len(v) - 1, max(0, int(math.ceil(q / 100.0 * len(v))) - 1))
+    return v[i]
+
+
+def run(args):
+    import numpy as np
+    import torch
+
+    import paper_2407_09812_amd as lib
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    sc = W.CONFIGS[args.config]()
+    K, N, M = sc.K, sc.N, sc.M
+    total = args.warmup + args.steps
+    log(f"bench: {sc.name} K={K} N={N} M={M} warmup={args.warmup} steps={args.steps}")
+
+    # device-resident inputs
+    refs = torch.tensor(np.stack([sc.x_ref(t) for t in range(total)]), dtype=torch.float32,
+                        device="cuda")
+    obs = lib.obstacles_to_device(sc.obstacles)
+    x_buf = [torch.tensor(sc.x0, dtype=torch.float32, device="cuda"),
+             torch.empty(17, dtype=torch.float32, device="cuda")]
+    u_nom = torch.tensor(sc.u_nom0(), dtype=torch.float32, device="cuda")
+    u_apply = torch.empty(8, dtype=torch.float32, device="cuda")
+    u_host = torch.empty(8, dtype=torch.float32, pin_memory=True)
+    diag = lib.new_diag()
+    ctx = lib.Context(0)
+    lib.mppi_reserve(ctx, K, N, M)
+    stream = torch.cuda.current_stream()
+    solves = [sc.solve(t) for t in range(total)]
+
+    lat = []
+
+    def step(t, record):
+        xi = x_buf[t % 2]
+        t0 = time.perf_counter()
+        lib.mppi_update(ctx, sc.veh, sc.cost, solves[t], xi, refs[t], obs, M, u_nom, u_apply, diag,
+                        stream=stream)
+        u_host.copy_(u_apply, non_blocking=True)
+        stream.synchronize()
+        t1 = time.perf_counter()
+        lib.mppi_plant_step(ctx, sc.veh, sc.dt, xi, u_apply, x_buf[(t + 1) % 2], stream=stream)
+        if record:
+            lat.append((t1 - t0) * 1e3)
+
+    for t in range(args.warmup):
+        step(t, False)
+    torch.cuda.synchronize()
+    lib.mppi_profile_enable(ctx, True)
+    lib.mppi_profile_read(ctx)                   # reset
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for t in range(args.warmup, total):
+        step(t, True)
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    prof = lib.mppi_profile_read(ctx)
+    lib.mppi_profile_enable(ctx, False)
+    d = lib.diag_from_tensor(diag)
+    final_x = x_buf[total % 2].cpu().numpy()
+    log(f"bench: final diag {d}, final position {final_x[:3]}")
+    if d["status"] != 0:
+        raise RuntimeError(f"update failed on device: {d}")
+
+    elapsed = t_end - t_start
+    steps = args.steps
+    value = K * N * steps / elapsed
+    n_upd = max(1, prof["updates"])
+    rollout_ms = prof["rollout_ms"] / n_upd
+    reduce_ms = prof["reduce_ms"] / n_upd
+    flop = rollout_flop_per_launch(K, N, M)
+    achieved = flop / (rollout_ms * 1e-3)
+    rbytes = reduction_bytes_per_launch(K, N)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "rollout-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{sc.name}: single vehicle, K={K}, N={N}, dt={sc.dt}, M={M}, "
+                               f"closed loop (plain: one solve per launch sequence)",
+                   "K": K, "N": N, "M": M, "updates": steps},
+        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99),
+                       "mean": sum(lat) / len(lat)},
+        "device_ms_per_update": {"rollout": rollout_ms, "weights": prof["weights_ms"] / n_upd,
+                                 "reduce": reduce_ms, "apply": prof["apply_ms"] / n_upd},
+        "roofline": {
+            "kernel": "rollout_kernel",
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_FP32_VECTOR / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VECTOR,
+            "frac_of_unpacked_peak": achieved / PEAK_FP32_UNPACKED,
+            "flop_per_launch": flop,
+            "traffic": measured_traffic(K, N, M),
+        },
+        "reduction": {"kernel": "weighted_sum_kernel", "bound": "hbm",
+                      "achieved": rbytes / (reduce_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
+                      "unit": "GB/s", "frac": rbytes / (reduce_ms * 1e-3) / PEAK_HBM,
+                      "bytes_per_launch": rbytes},
+    }
+    ctx.close()
+    if args.cpu_seconds > 0:
+        log(f"bench: timing the FP64 oracle for about {args.cpu_seconds:.0f} s")
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="oracle CPU-baseline time budget (0 skips it)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the MPPI update of one vehicle runs on one device; see the design notes "
+              "on sharding vehicles or samples over several GPUs).", file=sys.stderr)
+        sys.exit(2)
+    out = run(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,224 @@
+/*
+ * mppi.h -- C ABI of libmppi, an MI355X (gfx950) implementation of one Model
+ * Predictive Path Integral (MPPI) update for a quadrotor, after arXiv 2407.09812
+ * ("MPPI control for agile UAVs", Algorithm 1 and Sec. III).
+ *
+ * One update (Algorithm 1, loop body) takes the state estimate x_hat, the warm-start
+ * nominal sequence u_nom (N x 4), a reference trajectory and an obstacle list, and:
+ *   1. draws K perturbation sequences delta_u ~ N(0, diag(sigma^2))      Sec. III-A, Eq. (2)
+ *   2. rolls each through the quadrotor model with its rate controller,
+ *      allocation, rotor saturation and (optionally) rotor lag, by RK4     Eqs. (2), (6)-(13)
+ *   3. scores each rollout (input, input-change, tracking, obstacles)     Eqs. (3), (16)-(22)
+ *   4. turns costs into softmin weights with temperature lambda           Eq. (4)
+ *   5. forms u_nom += sum_k w_k delta_u^k                                 Eq. (5)
+ *   6. emits u_nom_0 (and the feasible [F_clip, omega_clip] at x_hat,
+ *      Eqs. (12)-(15)), shifts u_nom by one step and refills the last
+ *      slot with u_init                                                   Algorithm 1
+ *
+ * Conventions
+ *  - Every function returns mppi_status: MPPI_OK (0) or a negative error code.
+ *    No C++ exception crosses the ABI.  mppi_last_error() gives the text of the
+ *    last error on a context (HIP error strings included).
+ *  - Pointers documented as "device" are HIP device pointers (for example from
+ *    torch tensors' data_ptr()); the library never frees or retains them.  Pointers
+ *    documented as "host" are read during the call only.
+ *  - stream is a hipStream_t passed as void* (NULL = the null stream).  All device
+ *    work is enqueued asynchronously on it; nothing on the update path allocates
+ *    memory or synchronises the host.  Scratch is allocated by mppi_reserve().
+ *  - State layout (17 floats): [p(3) m, q(4) unit quaternion w-first (body to
+ *    world, Hamilton), v(3) m/s, omega(3) rad/s body frame, T(4) rotor thrusts N].
+ *    Control (4 floats): [F_t N, omega_d(3) rad/s].  Reference rows (13 floats):
+ *    [p, q, v, omega].  World z points up; gravity is (0, 0, -g).
+ *  - Arithmetic on the device is IEEE binary32 (FMA contraction allowed).
+ *  - One context per host thread.  Calls that share a context's scratch on
+ *    different streams must be ordered by the caller.
+ */
+#ifndef MPPI_H
+#define MPPI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mppi_status;
+
+enum {
+    MPPI_OK = 0,
+    MPPI_E_INVALID_ARG = -1,     /* bad size, parameter or NULL pointer               */
+    MPPI_E_NONFINITE_INPUT = -2, /* NaN/Inf in a host-side parameter                  */
+    MPPI_E_ALL_NONFINITE = -3,   /* every rollout cost non-finite: u_nom left as is   */
+    MPPI_E_BUDGET = -4,          /* request larger than the server's memory budget    */
+    MPPI_E_OOM = -5,             /* device allocation failed                          */
+    MPPI_E_HIP = -6,             /* HIP runtime error (see mppi_last_error)           */
+    MPPI_E_PENDING = -7,         /* result not ready yet                              */
+    MPPI_E_CAPACITY = -8         /* request exceeds the reserved scratch (reserve)    */
+};
+
+enum { MPPI_NX = 17, MPPI_NU = 4, MPPI_NREF = 13 };
+enum { MPPI_SPHERE = 0, MPPI_VCYLINDER = 1 };
+enum { MPPI_N_MAX = 4096, MPPI_M_MAX = 2048 };
+
+/* Vehicle model, Sec. III-B and Table I.  tau_m = 0 selects the paper's
+ * algebraic rotor model (clipped thrusts act at once, Eq. (13)); tau_m > 0 adds a
+ * first-order rotor lag T' = (T_cmd - T) / tau_m.  k_rate = 0 selects the
+ * rate-controller gain 1/dt of Eq. (8).  w_xy_max / w_z_max > 0 clamp the body
+ * rates of the applied output only (Sec. IV-A safety limits). */
+typedef struct mppi_vehicle {
+    float mass;
+    float J[3];
+    float arm_l;
+    float c_tf;
+    float g;
+    float T_min, T_max;
+    float tau_m;
+    float k_rate;
+    float w_xy_max, w_z_max;
+} mppi_vehicle;
+
+/* Cost, Eqs. (16)-(22) and Table II: input weights R, input-change weights R_d,
+ * tracking weights (c_p, c_v, c_q, c_w) with the attitude term c_q * d_q^2,
+ * d_q = 1 - <q, q_ref>^2 (Eq. (21)); obstacle term per state
+ * obs_collision * [inside any obstacle] + obs_w * sum_i max(0, r_i + obs_margin - d_i)^2. */
+typedef struct mppi_cost {
+    float c_p, c_v, c_q, c_w;
+    float R[4];
+    float R_d[4];
+    float obs_margin, obs_w, obs_collision;
+} mppi_cost;
+
+/* Obstacle (Sec. IV-D): sphere (distance |p - c|) or vertical cylinder of
+ * infinite height (distance |(p - c)_xy|), radius r. 20 bytes. */
+typedef struct mppi_obstacle {
+    int32_t type;
+    float c[3];
+    float r;
+} mppi_obstacle;
+
+/* Per-update problem (Algorithm 1 parameters).  sigma holds per-dimension standard
+ * deviations of delta_u.  Noise is Philox4x32-10 with key (seed low 32 bits,
+ * vehicle_id) and counter (k, j, t, seed high 32 bits), Box-Muller on the pairs
+ * of uniforms ((w >> 9) + 0.5) 2^-23; t is the vehicle's update index. */
+typedef struct mppi_solve {
+    int32_t K;         /* rollouts, >= 1                                  */
+    int32_t N;         /* horizon steps, 1..MPPI_N_MAX                    */
+    float dt;          /* prediction step, s, > 0                         */
+    float lambda;      /* softmin temperature, > 0                        */
+    float sigma[4];    /* noise standard deviations, >= 0                 */
+    float u_init[4];   /* refill value of the last slot after the shift   */
+    uint64_t seed;
+    uint32_t vehicle_id;
+    uint32_t t;
+} mppi_solve;
+
+/* Diagnostics written by the device (all rollouts of one update). */
+typedef struct mppi_diag {
+    float rho;         /* min_k S_k over finite costs                     */
+    float eta;         /* sum_k exp(-(S_k - rho) / lambda)                */
+    float ess;         /* effective sample size 1 / sum_k w_k^2           */
+    int32_t argmin;    /* smallest k with S_k = rho                       */
+    int32_t n_finite;  /* number of finite costs                          */
+    int32_t status;    /* MPPI_OK or MPPI_E_ALL_NONFINITE                 */
+    float reserved[2];
+} mppi_diag;
+
+typedef struct mppi_ctx mppi_ctx;
+
+/* Create a context on HIP device `device`.  Allocates no scratch yet. */
+mppi_status mppi_create(int device, mppi_ctx **out);
+mppi_status mppi_destroy(mppi_ctx *ctx);
+
+/* Make sure the context's scratch holds an update with up to K rollouts, N steps
+ * and M obstacles (delta_u [N][4][K] floats, costs and weights [K]).  The only call
+ * that allocates; it synchronises the device when it grows. */
+mppi_status mppi_reserve(mppi_ctx *ctx, int32_t K, int32_t N, int32_t M);
+
+/* Host-only argument check used by every entry point (no device access):
+ * MPPI_E_INVALID_ARG for K < 1, N < 1 or > MPPI_N_MAX, M < 0 or > MPPI_M_MAX,
+ * dt <= 0, lambda <= 0, sigma < 0, mass or inertia <= 0, T_min > T_max, tau_m < 0;
+ * MPPI_E_NONFINITE_INPUT for NaN/Inf parameters. */
+mppi_status mppi_validate(const mppi_vehicle *veh, const mppi_cost *cost,
+                          const mppi_solve *solve, int32_t M);
+
+/* One full MPPI update (Algorithm 1 loop body), asynchronous on `stream`.
+ *   x_hat    device, 17 floats                     state estimate
+ *   x_ref    device, (N+1) x 13 floats             reference rows j = 0..N
+ *   obs      device, M obstacles (may be NULL if M = 0)
+ *   u_nom    device, N x 4 floats, in/out          warm start -> updated and shifted
+ *   u_apply  device, 8 floats, out                 [u_nom_0 after the update (4),
+ *                                                   F_clip, omega_clip at x_hat (4)]
+ *   diag     device, one mppi_diag, out (may be NULL)
+ * When every cost is non-finite the device leaves u_nom unchanged, writes the
+ * current u_nom_0 to u_apply and sets diag->status = MPPI_E_ALL_NONFINITE.
+ * Returns MPPI_E_CAPACITY if K, N or M exceed the reserved scratch. */
+mppi_status mppi_update(mppi_ctx *ctx, void *stream, const mppi_vehicle *veh,
+                        const mppi_cost *cost, const mppi_solve *solve,
+                        const float *x_hat, const float *x_ref,
+                        const mppi_obstacle *obs, int32_t M,
+                        float *u_nom, float *u_apply, mppi_diag *diag);
+
+/* --- the update's stages, exposed for stage-by-stage checking ------------------ */
+
+/* Rollouts and costs (Eqs. (2), (3)): writes delta_u [N][4][ld] (device, row
+ * (j, d) holds samples k = 0..K-1 contiguously, ld >= K), S [K] (device) and, if
+ * states is not NULL, the trajectories [N+1][17][ld] (device). */
+mppi_status mppi_rollout(mppi_ctx *ctx, void *stream, const mppi_vehicle *veh,
+                         const mppi_cost *cost, const mppi_solve *solve,
+                         const float *x_hat, const float *x_ref,
+                         const mppi_obstacle *obs, int32_t M, const float *u_nom,
+                         float *du, int32_t ld, float *S, float *states);
+
+/* Softmin weights (Eq. (4)) of S [K] (device): w [K] (device), diag (device). */
+mppi_status mppi_weights(mppi_ctx *ctx, void *stream, int32_t K, const float *S,
+                         float lambda, float *w, mppi_diag *diag);
+
+/* Weighted update (Eq. (5)): u_out[j][d] = u_in[j][d] + sum_k w[k] du[j][d][k]
+ * (all device; du as written by mppi_rollout with leading dimension ld).  If diag
+ * is not NULL and diag->status != MPPI_OK, u_out = u_in. u_out may alias u_in. */
+mppi_status mppi_weighted_sum(mppi_ctx *ctx, void *stream, int32_t K, int32_t N,
+                              const float *w, const float *du, int32_t ld,
+                              const float *u_in, float *u_out, const mppi_diag *diag);
+
+/* Apply and shift (Algorithm 1 after Eq. (5); Eqs. (12)-(15)): u_apply[0..3] =
+ * u_upd[0], u_apply[4..7] = [F_clip, omega_clip] at x_hat; u_nom[j] = u_upd[j+1],
+ * u_nom[N-1] = solve->u_init.  Device pointers; u_nom may alias u_upd. */
+mppi_status mppi_apply_shift(mppi_ctx *ctx, void *stream, const mppi_vehicle *veh,
+                             const mppi_solve *solve, const float *x_hat,
+                             const float *u_upd, float *u_nom, float *u_apply);
+
+/* The noise of one update as the rollout kernel draws it: du [N][4][ld] (device). */
+mppi_status mppi_noise(mppi_ctx *ctx, void *stream, const mppi_solve *solve,
+                       float *du, int32_t ld);
+
+/* Raw Philox4x32-10 on the device: out[i] = philox(ctr[i], key[i]) for n
+ * counters (ctr, out: n x 4 uint32; key: n x 2 uint32; all device). */
+mppi_status mppi_philox(mppi_ctx *ctx, void *stream, int32_t n, const uint32_t *ctr,
+                        const uint32_t *key, uint32_t *out);
+
+/* One noise-free model step of the plant, x_out = x + f_RK4(x, u, dt) with the
+ * rate controller inside (Eq. (2), last line): x, u, x_out device (17, 4, 17). */
+mppi_status mppi_plant_step(mppi_ctx *ctx, void *stream, const mppi_vehicle *veh, float dt,
+                            const float *x, const float *u, float *x_out);
+
+/* --- profiling ---------------------------------------------------------------- */
+
+/* Per-kernel device time of mppi_update, measured with HIP events on the
+ * update's stream while enabled. */
+typedef struct mppi_profile {
+    int64_t updates;
+    double rollout_ms, weights_ms, reduce_ms, apply_ms;
+} mppi_profile;
+
+mppi_status mppi_profile_enable(mppi_ctx *ctx, int32_t on);
+/* Waits for the recorded events, returns the totals since enable and resets them. */
+mppi_status mppi_profile_read(mppi_ctx *ctx, mppi_profile *out);
+
+const char *mppi_status_str(mppi_status s);
+const char *mppi_last_error(const mppi_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPPI_H */

@@ -39,6 +39,7 @@ def _load():
     lib = C.CDLL(_build.LIB)
     dp = C.POINTER(C.c_double)
     up = C.POINTER(C.c_uint32)
+    ip = C.POINTER(C.c_int32)
     i32, u32, u64, f64 = C.c_int, C.c_uint32, C.c_uint64, C.c_double
     sig = {
         "orc_philox4x32_10": (None, [up, up, up]),
@@ -58,6 +59,10 @@ def _load():
         "orc_trajectory_cost": (f64, [dp, i32, dp, dp, dp, dp, i32]),
         "orc_rollouts": (None, [dp, dp, i32, i32, f64, dp, u64, u32, u32,
                                 dp, dp, dp, dp, i32, dp, dp, dp]),
+        "orc_rollouts_subset": (None, [dp, dp, i32, ip, i32, f64, dp, u64, u32, u32,
+                                       dp, dp, dp, dp, i32, dp, dp, dp]),
+        "orc_philox_many": (None, [i32, up, up, up]),
+        "orc_num_threads": (i32, []),
         "orc_weights": (i32, [i32, dp, f64, dp, dp]),
         "orc_weighted_update": (None, [i32, i32, dp, dp, dp]),
         "orc_apply_shift": (None, [dp, i32, f64, dp, dp, dp, dp]),
@@ -115,6 +120,22 @@ def philox4x32_10(ctr, key):
     o = (C.c_uint32 * 4)()
     lib.orc_philox4x32_10(c, k, o)
     return [int(v) for v in o]
+
+
+def num_threads() -> int:
+    """Threads the oracle's per-sample loop uses."""
+    return int(_load().orc_num_threads())
+
+
+def philox_many(ctr, key):
+    """Philox4x32-10 of n counters [n, 4] with keys [n, 2] (uint32) -> [n, 4]."""
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    key = np.ascontiguousarray(key, dtype=np.uint32).reshape(-1, 2)
+    out = np.empty_like(ctr)
+    up = C.POINTER(C.c_uint32)
+    _load().orc_philox_many(ctr.shape[0], ctr.ctypes.data_as(up), key.ctypes.data_as(up),
+                            out.ctypes.data_as(up))
+    return out
 
 
 def uniform(w: int) -> float:
@@ -225,6 +246,27 @@ def rollouts(veh, cost, solve, x_hat, u_nom, x_ref, obs=None, want_states=False)
     _load().orc_rollouts(_p(v), _p(c), K, N, float(solve["dt"]), _p(s), int(solve["seed"]),
                          int(solve.get("vehicle_id", 0)), int(solve.get("t", 0)),
                          _p(xh), _p(un), _p(xr), _p(o), o.shape[0], _p(states), _p(du), _p(S))
+    return states, du, S
+
+
+def rollouts_subset(veh, cost, solve, ks, x_hat, u_nom, x_ref, obs=None, want_states=True):
+    """Rollouts of the sample indices ks only: (states [n, N+1, 17] or None,
+    du [n, N, 4], S [n])."""
+    N = int(solve["N"])
+    ks = np.ascontiguousarray(ks, dtype=np.int32)
+    v, c = vehicle_array(veh), cost_array(cost)
+    s = _d(solve["sigma"], 4)
+    xh, un, xr = _d(x_hat, NX), _d(u_nom, N * 4), _d(x_ref, (N + 1) * 13)
+    o = obstacle_array(obs)
+    n = ks.size
+    states = np.empty((n, N + 1, NX)) if want_states else None
+    du = np.empty((n, N, 4))
+    S = np.empty(n)
+    _load().orc_rollouts_subset(_p(v), _p(c), n, ks.ctypes.data_as(C.POINTER(C.c_int32)), N,
+                                float(solve["dt"]), _p(s), int(solve["seed"]),
+                                int(solve.get("vehicle_id", 0)), int(solve.get("t", 0)),
+                                _p(xh), _p(un), _p(xr), _p(o), o.shape[0], _p(states), _p(du),
+                                _p(S))
     return states, du, S
 
 

@@ -40,6 +40,7 @@
  *    Algorithm 1 (hover, (m g, 0, 0, 0), in the paper).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -130,6 +131,12 @@ void orc_noise_one(int k, int j, const double sigma[4], uint64_t seed,
     z[2] = r1 * cos(two_pi * u3);
     z[3] = r1 * sin(two_pi * u3);
     for (int d = 0; d < 4; ++d) du[d] = sigma[d] * z[d];
+}
+
+/* n independent Philox calls: ctr [n][4], key [n][2], out [n][4]. */
+void orc_philox_many(int n, const uint32_t *ctr, const uint32_t *key, uint32_t *out)
+{
+    for (int i = 0; i < n; ++i) orc_philox4x32_10(ctr + 4 * (size_t)i, key + 2 * (size_t)i, out + 4 * (size_t)i);
 }
 
 /* du laid out [K][N][4]. */
@@ -399,33 +406,57 @@ double orc_trajectory_cost(const double *cost, int N, const double *states, cons
 /* The MPPI iteration (Algorithm 1).                                        */
 /* ------------------------------------------------------------------------ */
 
-/* K rollouts from x_hat (Eq. (2)) and their costs (Eq. (3)).
- * u_nom [N][4]; x_ref [N+1][13]; outputs du [K][N][4], S [K] and, when not
- * NULL, states [K][N+1][17].  Samples are independent, so the loop over k
- * may run on several threads without changing any result. */
+/* Rollout k from x_hat (Eq. (2)) and its cost (Eq. (3)): du_k [N][4],
+ * returns S_k; traj (may be NULL) receives the states [N+1][17]. */
+double orc_rollout_one(const double *veh, const double *cost, int k, int N, double dt,
+                       const double sigma[4], uint64_t seed, uint32_t vehicle_id, uint32_t t,
+                       const double *x_hat, const double *u_nom, const double *x_ref,
+                       const double *obs, int M, double *traj_out, double *du_k)
+{
+    double *traj = (double *)malloc(sizeof(double) * (size_t)(N + 1) * ORC_NX);
+    double *uk = (double *)malloc(sizeof(double) * (size_t)N * 4);
+    memcpy(traj, x_hat, sizeof(double) * ORC_NX);
+    for (int j = 0; j < N; ++j) {
+        orc_noise_one(k, j, sigma, seed, vehicle_id, t, du_k + j * 4);
+        for (int d = 0; d < 4; ++d) uk[j * 4 + d] = u_nom[j * 4 + d] + du_k[j * 4 + d];
+        orc_model_step(veh, traj + (size_t)j * ORC_NX, uk + j * 4, dt,
+                       traj + (size_t)(j + 1) * ORC_NX);
+    }
+    double S = orc_trajectory_cost(cost, N, traj, uk, x_ref, obs, M);
+    if (traj_out) memcpy(traj_out, traj, sizeof(double) * (size_t)(N + 1) * ORC_NX);
+    free(uk);
+    free(traj);
+    return S;
+}
+
+/* K rollouts and their costs.  u_nom [N][4]; x_ref [N+1][13]; outputs du
+ * [K][N][4], S [K] and, when not NULL, states [K][N+1][17].  Samples are
+ * independent, so the loop over k may run on several threads without changing
+ * any result. */
 void orc_rollouts(const double *veh, const double *cost, int K, int N, double dt,
                   const double sigma[4], uint64_t seed, uint32_t vehicle_id, uint32_t t,
                   const double *x_hat, const double *u_nom, const double *x_ref,
                   const double *obs, int M, double *states, double *du, double *S)
 {
 #pragma omp parallel for schedule(dynamic, 16)
-    for (int k = 0; k < K; ++k) {
-        double *traj = (double *)malloc(sizeof(double) * (size_t)(N + 1) * ORC_NX);
-        double *uk = (double *)malloc(sizeof(double) * (size_t)N * 4);
-        double *duk = du + (size_t)k * N * 4;
-        memcpy(traj, x_hat, sizeof(double) * ORC_NX);
-        for (int j = 0; j < N; ++j) {
-            orc_noise_one(k, j, sigma, seed, vehicle_id, t, duk + j * 4);
-            for (int d = 0; d < 4; ++d) uk[j * 4 + d] = u_nom[j * 4 + d] + duk[j * 4 + d];
-            orc_model_step(veh, traj + (size_t)j * ORC_NX, uk + j * 4, dt,
-                           traj + (size_t)(j + 1) * ORC_NX);
-        }
-        S[k] = orc_trajectory_cost(cost, N, traj, uk, x_ref, obs, M);
-        if (states) memcpy(states + (size_t)k * (N + 1) * ORC_NX, traj,
-                           sizeof(double) * (size_t)(N + 1) * ORC_NX);
-        free(uk);
-        free(traj);
-    }
+    for (int k = 0; k < K; ++k)
+        S[k] = orc_rollout_one(veh, cost, k, N, dt, sigma, seed, vehicle_id, t, x_hat, u_nom,
+                               x_ref, obs, M, states ? states + (size_t)k * (N + 1) * ORC_NX : NULL,
+                               du + (size_t)k * N * 4);
+}
+
+/* The rollouts of the listed sample indices only (outputs indexed like ks). */
+void orc_rollouts_subset(const double *veh, const double *cost, int nk, const int *ks, int N,
+                         double dt, const double sigma[4], uint64_t seed, uint32_t vehicle_id,
+                         uint32_t t, const double *x_hat, const double *u_nom,
+                         const double *x_ref, const double *obs, int M, double *states,
+                         double *du, double *S)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int i = 0; i < nk; ++i)
+        S[i] = orc_rollout_one(veh, cost, ks[i], N, dt, sigma, seed, vehicle_id, t, x_hat, u_nom,
+                               x_ref, obs, M, states ? states + (size_t)i * (N + 1) * ORC_NX : NULL,
+                               du + (size_t)i * N * 4);
 }
 
 /* Softmin weights, Eq. (4).  Returns 0, or -1 when no cost is finite.
@@ -496,4 +527,10 @@ int orc_update(const double *veh, const double *cost, int K, int N, double dt, d
     if (!S_out) free(S);
     if (!w_out) free(w);
     return rc;
+}
+
+/* Threads the per-sample loop runs on (OpenMP; OMP_NUM_THREADS). */
+int orc_num_threads(void)
+{
+    return omp_get_max_threads();
 }

@@ -1,0 +1,295 @@
+"""Python binding of libmppi, the MI355X (gfx950) MPPI update library.
+
+Argument marshalling only: every step of the update runs in the HIP kernels behind
+the C ABI declared in ``include/mppi.h``.  PyTorch supplies device memory and
+streams.  Importing this package loads ``libmppi.so`` from the package directory and
+raises if it is missing -- there is no CPU fallback.
+
+Function names follow the C ABI (``mppi_update``, ``mppi_rollout``, ...).
+Parameter dictionaries use the keys of ``include/mppi.h``'s structs:
+  vehicle: mass, J, arm_l, c_tf, g, T_min, T_max, tau_m, k_rate, w_xy_max, w_z_max
+  cost:    c_p, c_v, c_q, c_w, R, R_d, obs_margin, obs_w, obs_collision
+  solve:   K, N, dt, lam, sigma, u_init, seed, vehicle_id, t
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmppi.so")
+
+MPPI_OK = 0
+STATUS = {0: "MPPI_OK", -1: "MPPI_E_INVALID_ARG", -2: "MPPI_E_NONFINITE_INPUT",
+          -3: "MPPI_E_ALL_NONFINITE", -4: "MPPI_E_BUDGET", -5: "MPPI_E_OOM", -6: "MPPI_E_HIP",
+          -7: "MPPI_E_PENDING", -8: "MPPI_E_CAPACITY"}
+NX, NU, NREF = 17, 4, 13
+N_MAX, M_MAX = 4096, 2048
+SPHERE, VCYLINDER = 0, 1
+
+
+class MPPIError(RuntimeError):
+    def __init__(self, status, where, detail=""):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)} {detail}".strip())
+
+
+# --- C structs (layouts of include/mppi.h) ----------------------------------
+
+class Vehicle(C.Structure):
+    _fields_ = [("mass", C.c_float), ("J", C.c_float * 3), ("arm_l", C.c_float),
+                ("c_tf", C.c_float), ("g", C.c_float), ("T_min", C.c_float), ("T_max", C.c_float),
+                ("tau_m", C.c_float), ("k_rate", C.c_float), ("w_xy_max", C.c_float),
+                ("w_z_max", C.c_float)]
+
+
+class Cost(C.Structure):
+    _fields_ = [("c_p", C.c_float), ("c_v", C.c_float), ("c_q", C.c_float), ("c_w", C.c_float),
+                ("R", C.c_float * 4), ("R_d", C.c_float * 4), ("obs_margin", C.c_float),
+                ("obs_w", C.c_float), ("obs_collision", C.c_float)]
+
+
+class Solve(C.Structure):
+    _fields_ = [("K", C.c_int32), ("N", C.c_int32), ("dt", C.c_float), ("lam", C.c_float),
+                ("sigma", C.c_float * 4), ("u_init", C.c_float * 4), ("seed", C.c_uint64),
+                ("vehicle_id", C.c_uint32), ("t", C.c_uint32)]
+
+
+class Diag(C.Structure):
+    _fields_ = [("rho", C.c_float), ("eta", C.c_float), ("ess", C.c_float),
+                ("argmin", C.c_int32), ("n_finite", C.c_int32), ("status", C.c_int32),
+                ("reserved", C.c_float * 2)]
+
+
+class Profile(C.Structure):
+    _fields_ = [("updates", C.c_int64), ("rollout_ms", C.c_double), ("weights_ms", C.c_double),
+                ("reduce_ms", C.c_double), ("apply_ms", C.c_double)]
+
+
+OBSTACLE_DTYPE = np.dtype([("type", "<i4"), ("c", "<f4", (3,)), ("r", "<f4")])
+assert OBSTACLE_DTYPE.itemsize == 20 and C.sizeof(Diag) == 32
+
+# --- library ------------------------------------------------------------------
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
+                      "g.build()'` (hipcc, gfx950); there is no fallback path")
+_lib = C.CDLL(LIB_PATH)
+
+_vp, _i32, _f32 = C.c_void_p, C.c_int32, C.c_float
+_PV, _PC, _PS = C.POINTER(Vehicle), C.POINTER(Cost), C.POINTER(Solve)
+_SIGS = {
+    "mppi_create": [C.c_int, C.POINTER(_vp)],
+    "mppi_destroy": [_vp],
+    "mppi_reserve": [_vp, _i32, _i32, _i32],
+    "mppi_validate": [_PV, _PC, _PS, _i32],
+    "mppi_update": [_vp, _vp, _PV, _PC, _PS, _vp, _vp, _vp, _i32, _vp, _vp, _vp],
+    "mppi_rollout": [_vp, _vp, _PV, _PC, _PS, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _vp],
+    "mppi_weights": [_vp, _vp, _i32, _vp, _f32, _vp, _vp],
+    "mppi_weighted_sum": [_vp, _vp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _vp],
+    "mppi_apply_shift": [_vp, _vp, _PV, _PS, _vp, _vp, _vp, _vp],
+    "mppi_noise": [_vp, _vp, _PS, _vp, _i32],
+    "mppi_philox": [_vp, _vp, _i32, _vp, _vp, _vp],
+    "mppi_plant_step": [_vp, _vp, _PV, _f32, _vp, _vp, _vp],
+    "mppi_profile_enable": [_vp, _i32],
+    "mppi_profile_read": [_vp, C.POINTER(Profile)],
+}
+for _name, _args in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = C.c_int32
+_lib.mppi_status_str.argtypes = [C.c_int32]
+_lib.mppi_status_str.restype = C.c_char_p
+_lib.mppi_last_error.argtypes = [_vp]
+_lib.mppi_last_error.restype = C.c_char_p
+
+
+def exported_symbols():
+    """Names of the C ABI entry points this binding resolves."""
+    return sorted(list(_SIGS) + ["mppi_status_str", "mppi_last_error"])
+
+
+# --- marshalling ----------------------------------------------------------------
+
+def vehicle(d: dict) -> Vehicle:
+    v = Vehicle()
+    v.mass = d["mass"]; v.J = (C.c_float * 3)(*d["J"]); v.arm_l = d["arm_l"]; v.c_tf = d["c_tf"]
+    v.g = d["g"]; v.T_min = d["T_min"]; v.T_max = d["T_max"]; v.tau_m = d["tau_m"]
+    v.k_rate = d.get("k_rate", 0.0); v.w_xy_max = d.get("w_xy_max", 0.0)
+    v.w_z_max = d.get("w_z_max", 0.0)
+    return v
+
+
+def cost(d: dict) -> Cost:
+    c = Cost()
+    c.c_p, c.c_v, c.c_q, c.c_w = d["c_p"], d["c_v"], d["c_q"], d["c_w"]
+    c.R = (C.c_float * 4)(*d["R"]); c.R_d = (C.c_float * 4)(*d["R_d"])
+    c.obs_margin, c.obs_w, c.obs_collision = d["obs_margin"], d["obs_w"], d["obs_collision"]
+    return c
+
+
+def solve(d: dict) -> Solve:
+    s = Solve()
+    s.K, s.N, s.dt, s.lam = int(d["K"]), int(d["N"]), float(d["dt"]), float(d["lam"])
+    s.sigma = (C.c_float * 4)(*[float(v) for v in d["sigma"]])
+    s.u_init = (C.c_float * 4)(*[float(v) for v in d["u_init"]])
+    s.seed = int(d["seed"]) & 0xFFFFFFFFFFFFFFFF
+    s.vehicle_id = int(d.get("vehicle_id", 0)) & 0xFFFFFFFF
+    s.t = int(d.get("t", 0)) & 0xFFFFFFFF
+    return s
+
+
+def obstacles_to_device(obs, device="cuda") -> torch.Tensor:
+    """[M, 5] rows (type, cx, cy, cz, r) -> device buffer of mppi_obstacle structs."""
+    obs = np.asarray(obs, dtype=np.float64).reshape(-1, 5)
+    rec = np.zeros(obs.shape[0], dtype=OBSTACLE_DTYPE)
+    rec["type"] = obs[:, 0].astype(np.int32)
+    rec["c"] = obs[:, 1:4].astype(np.float32)
+    rec["r"] = obs[:, 4].astype(np.float32)
+    raw = np.frombuffer(rec.tobytes(), dtype=np.uint8).copy()
+    if raw.size == 0:
+        raw = np.zeros(4, dtype=np.uint8)
+    return torch.from_numpy(raw).to(device)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("device tensors must be contiguous CUDA/HIP tensors")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def diag_from_tensor(t: torch.Tensor) -> dict:
+    raw = t.detach().cpu().numpy().tobytes()
+    d = Diag.from_buffer_copy(raw[:C.sizeof(Diag)])
+    return dict(rho=d.rho, eta=d.eta, ess=d.ess, argmin=d.argmin, n_finite=d.n_finite,
+                status=d.status)
+
+
+def new_diag(device="cuda") -> torch.Tensor:
+    return torch.zeros(C.sizeof(Diag), dtype=torch.uint8, device=device)
+
+
+# --- entry points ---------------------------------------------------------------
+
+class Context:
+    """An mppi_ctx on one device (owns the update's scratch)."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        st = _lib.mppi_create(int(device), C.byref(h))
+        if st != MPPI_OK:
+            raise MPPIError(st, "mppi_create")
+        self.handle = h
+        self.device = device
+
+    def check(self, st, where):
+        if st != MPPI_OK:
+            raise MPPIError(st, where, _lib.mppi_last_error(self.handle).decode())
+
+    def close(self):
+        if self.handle:
+            _lib.mppi_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mppi_create(device: int = 0) -> Context:
+    return Context(device)
+
+
+def mppi_destroy(ctx: Context):
+    ctx.close()
+
+
+def mppi_reserve(ctx: Context, K: int, N: int, M: int):
+    ctx.check(_lib.mppi_reserve(ctx.handle, int(K), int(N), int(M)), "mppi_reserve")
+
+
+def mppi_validate(veh: dict, cst: dict, slv: dict, M: int) -> int:
+    """Host-only argument check; returns the status code."""
+    v, c, s = vehicle(veh), cost(cst), solve(slv)
+    return int(_lib.mppi_validate(C.byref(v), C.byref(c), C.byref(s), int(M)))
+
+
+def mppi_update(ctx, veh, cst, slv, x_hat, x_ref, obs_dev, M, u_nom, u_apply, diag=None,
+                stream=None):
+    v, c, s = vehicle(veh), cost(cst), solve(slv)
+    ctx.check(_lib.mppi_update(ctx.handle, _stream(stream), C.byref(v), C.byref(c), C.byref(s),
+                               _ptr(x_hat), _ptr(x_ref), _ptr(obs_dev) if M > 0 else None, int(M),
+                               _ptr(u_nom), _ptr(u_apply), _ptr(diag)), "mppi_update")
+
+
+def mppi_rollout(ctx, veh, cst, slv, x_hat, x_ref, obs_dev, M, u_nom, du, ld, S, states=None,
+                 stream=None):
+    v, c, s = vehicle(veh), cost(cst), solve(slv)
+    ctx.check(_lib.mppi_rollout(ctx.handle, _stream(stream), C.byref(v), C.byref(c), C.byref(s),
+                                _ptr(x_hat), _ptr(x_ref), _ptr(obs_dev) if M > 0 else None,
+                                int(M), _ptr(u_nom), _ptr(du), int(ld), _ptr(S), _ptr(states)),
+              "mppi_rollout")
+
+
+def mppi_weights(ctx, K, S, lam, w, diag, stream=None):
+    ctx.check(_lib.mppi_weights(ctx.handle, _stream(stream), int(K), _ptr(S), float(lam), _ptr(w),
+                                _ptr(diag)), "mppi_weights")
+
+
+def mppi_weighted_sum(ctx, K, N, w, du, ld, u_in, u_out, diag=None, stream=None):
+    ctx.check(_lib.mppi_weighted_sum(ctx.handle, _stream(stream), int(K), int(N), _ptr(w), _ptr(du),
+                                     int(ld), _ptr(u_in), _ptr(u_out), _ptr(diag)),
+              "mppi_weighted_sum")
+
+
+def mppi_apply_shift(ctx, veh, slv, x_hat, u_upd, u_nom, u_apply, stream=None):
+    v, s = vehicle(veh), solve(slv)
+    ctx.check(_lib.mppi_apply_shift(ctx.handle, _stream(stream), C.byref(v), C.byref(s),
+                                    _ptr(x_hat), _ptr(u_upd), _ptr(u_nom), _ptr(u_apply)),
+              "mppi_apply_shift")
+
+
+def mppi_noise(ctx, slv, du, ld, stream=None):
+    s = solve(slv)
+    ctx.check(_lib.mppi_noise(ctx.handle, _stream(stream), C.byref(s), _ptr(du), int(ld)),
+              "mppi_noise")
+
+
+def mppi_philox(ctx, ctr, key, out, stream=None):
+    n = ctr.shape[0]
+    ctx.check(_lib.mppi_philox(ctx.handle, _stream(stream), int(n), _ptr(ctr), _ptr(key), _ptr(out)),
+              "mppi_philox")
+
+
+def mppi_plant_step(ctx, veh, dt, x, u, x_out, stream=None):
+    v = vehicle(veh)
+    ctx.check(_lib.mppi_plant_step(ctx.handle, _stream(stream), C.byref(v), float(dt), _ptr(x),
+                                   _ptr(u), _ptr(x_out)), "mppi_plant_step")
+
+
+def mppi_profile_enable(ctx, on=True):
+    ctx.check(_lib.mppi_profile_enable(ctx.handle, 1 if on else 0), "mppi_profile_enable")
+
+
+def mppi_profile_read(ctx) -> dict:
+    p = Profile()
+    ctx.check(_lib.mppi_profile_read(ctx.handle, C.byref(p)), "mppi_profile_read")
+    return dict(updates=p.updates, rollout_ms=p.rollout_ms, weights_ms=p.weights_ms,
+                reduce_ms=p.reduce_ms, apply_ms=p.apply_ms)
+
+
+def mppi_status_str(st: int) -> str:
+    return _lib.mppi_status_str(int(st)).decode()

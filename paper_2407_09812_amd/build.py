@@ -1,0 +1,44 @@
+"""Build libmppi.so (HIP, gfx950) in-tree with hipcc.
+
+Packed FP32 instructions are disabled (-packed-fp32-ops); everything else is
+plain -O3 HIP for one target, gfx950.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "api.hip")]
+HEADERS = [os.path.join(CSRC, f) for f in ("kernels.h", "model.h")] + [
+    os.path.join(ROOT, "include", "mppi.h")]
+LIB = os.path.join(HERE, "libmppi.so")
+ARCH = os.environ.get("MPPI_OFFLOAD_ARCH", "gfx950")
+
+
+def hipcc_flags():
+    return ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
+
+
+def build(verbose: bool = False) -> str:
+    tmp = LIB + ".tmp"
+    cmd = ["hipcc", *hipcc_flags(), "-shared", "-o", tmp, *SOURCES]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def is_stale() -> bool:
+    if not os.path.exists(LIB):
+        return True
+    t = os.path.getmtime(LIB)
+    return any(os.path.getmtime(f) > t for f in SOURCES + HEADERS)
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

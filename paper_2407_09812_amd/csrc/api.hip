@@ -1,0 +1,433 @@
+// C ABI of libmppi (declared in include/mppi.h): argument validation, device
+// scratch, launch sequencing of one MPPI update, profiling and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace mppi;
+
+struct mppi_ctx {
+    int device = 0;
+    int K_cap = 0, N_cap = 0, M_cap = 0, ld = 0;
+    float* du = nullptr;        // [N_cap][4][ld]
+    float* S = nullptr;         // [ld]
+    float* w = nullptr;         // [ld]
+    float* u_upd = nullptr;     // [N_cap][4]
+    mppi_diag* diag = nullptr;  // 1
+    int rollout_block = 64;
+    std::string last_error;
+    // profiling: 5 events per update bracket rollout, weights, sum, apply
+    bool profiling = false;
+    std::vector<hipEvent_t> pool, pending;
+    mppi_profile acc{};
+};
+
+namespace {
+
+constexpr int kEventsPerUpdate = 5;
+
+mppi_status fail(mppi_ctx* ctx, mppi_status s, const std::string& msg)
+{
+    if (ctx) ctx->last_error = msg;
+    return s;
+}
+
+mppi_status hip_fail(mppi_ctx* ctx, hipError_t e, const char* where)
+{
+    return fail(ctx, MPPI_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                                   \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+bool finite_all(const float* v, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+mppi_status check_vehicle(const mppi_vehicle* v)
+{
+    if (!v) return MPPI_E_INVALID_ARG;
+    const float vals[13] = {v->mass, v->J[0], v->J[1], v->J[2], v->arm_l, v->c_tf, v->g,
+                            v->T_min, v->T_max, v->tau_m, v->k_rate, v->w_xy_max, v->w_z_max};
+    if (!finite_all(vals, 13)) return MPPI_E_NONFINITE_INPUT;
+    if (!(v->mass > 0) || !(v->J[0] > 0) || !(v->J[1] > 0) || !(v->J[2] > 0)) return MPPI_E_INVALID_ARG;
+    if (!(v->arm_l > 0) || !(v->c_tf > 0) || v->T_min > v->T_max) return MPPI_E_INVALID_ARG;
+    if (v->tau_m < 0 || v->k_rate < 0 || v->w_xy_max < 0 || v->w_z_max < 0) return MPPI_E_INVALID_ARG;
+    return MPPI_OK;
+}
+
+mppi_status check_cost(const mppi_cost* c)
+{
+    if (!c) return MPPI_E_INVALID_ARG;
+    const float vals[15] = {c->c_p, c->c_v, c->c_q, c->c_w, c->R[0], c->R[1], c->R[2], c->R[3],
+                            c->R_d[0], c->R_d[1], c->R_d[2], c->R_d[3], c->obs_margin, c->obs_w,
+                            c->obs_collision};
+    if (!finite_all(vals, 15)) return MPPI_E_NONFINITE_INPUT;
+    for (float x : vals)
+        if (x < 0) return MPPI_E_INVALID_ARG;
+    return MPPI_OK;
+}
+
+mppi_status check_solve(const mppi_solve* s)
+{
+    if (!s) return MPPI_E_INVALID_ARG;
+    if (s->K < 1 || s->N < 1 || s->N > MPPI_N_MAX) return MPPI_E_INVALID_ARG;
+    const float vals[10] = {s->dt, s->lambda, s->sigma[0], s->sigma[1], s->sigma[2], s->sigma[3],
+                            s->u_init[0], s->u_init[1], s->u_init[2], s->u_init[3]};
+    if (!finite_all(vals, 10)) return MPPI_E_NONFINITE_INPUT;
+    if (!(s->dt > 0) || !(s->lambda > 0)) return MPPI_E_INVALID_ARG;
+    for (int d = 0; d < 4; ++d)
+        if (s->sigma[d] < 0) return MPPI_E_INVALID_ARG;
+    return MPPI_OK;
+}
+
+ModelParams model_params(const mppi_vehicle& v, float dt)
+{
+    ModelParams P{};
+    const double s = (double)v.arm_l / std::sqrt(2.0);
+    P.m_inv = (float)(1.0 / v.mass);
+    P.g = v.g;
+    for (int i = 0; i < 3; ++i) {
+        P.J[i] = v.J[i];
+        P.J_inv[i] = (float)(1.0 / v.J[i]);
+    }
+    P.G[0] = v.J[2] - v.J[1];
+    P.G[1] = v.J[0] - v.J[2];
+    P.G[2] = v.J[1] - v.J[0];
+    P.s = (float)s;
+    P.c = v.c_tf;
+    P.inv_4s = (float)(1.0 / (4.0 * s));
+    P.inv_4c = (float)(1.0 / (4.0 * v.c_tf));
+    P.T_min = v.T_min;
+    P.T_max = v.T_max;
+    P.lag = v.tau_m > 0.0f ? 1 : 0;
+    P.tau_inv = P.lag ? (float)(1.0 / v.tau_m) : 0.0f;
+    P.k_w = v.k_rate > 0.0f ? v.k_rate : (float)(1.0 / dt);
+    P.dt = dt;
+    P.w_xy_max = v.w_xy_max;
+    P.w_z_max = v.w_z_max;
+    return P;
+}
+
+CostParams cost_params(const mppi_cost& c)
+{
+    CostParams C{};
+    C.c_p = c.c_p; C.c_v = c.c_v; C.c_q = c.c_q; C.c_w = c.c_w;
+    for (int d = 0; d < 4; ++d) { C.R[d] = c.R[d]; C.Rd[d] = c.R_d[d]; }
+    C.margin = c.obs_margin; C.w_obs = c.obs_w; C.c_col = c.obs_collision;
+    return C;
+}
+
+NoiseParams noise_params(const mppi_solve& s)
+{
+    NoiseParams np{};
+    for (int d = 0; d < 4; ++d) np.sigma[d] = s.sigma[d];
+    np.key0 = (uint32_t)(s.seed & 0xFFFFFFFFull);
+    np.key1 = s.vehicle_id;
+    np.t = s.t;
+    np.seed_hi = (uint32_t)(s.seed >> 32);
+    return np;
+}
+
+RolloutArgs rollout_args(const mppi_vehicle& v, const mppi_cost& c, const mppi_solve& s)
+{
+    RolloutArgs a{};
+    a.mp = model_params(v, s.dt);
+    a.cp = cost_params(c);
+    a.np = noise_params(s);
+    a.K = s.K;
+    a.N = s.N;
+    return a;
+}
+
+void free_scratch(mppi_ctx* ctx)
+{
+    (void)hipFree(ctx->du); (void)hipFree(ctx->S); (void)hipFree(ctx->w);
+    (void)hipFree(ctx->u_upd); (void)hipFree(ctx->diag);
+    ctx->du = ctx->S = ctx->w = ctx->u_upd = nullptr;
+    ctx->diag = nullptr;
+    ctx->K_cap = ctx->N_cap = ctx->M_cap = ctx->ld = 0;
+}
+
+hipEvent_t take_event(mppi_ctx* ctx)
+{
+    if (!ctx->pool.empty()) {
+        hipEvent_t e = ctx->pool.back();
+        ctx->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mppi_status_str(mppi_status s)
+{
+    switch (s) {
+    case MPPI_OK: return "MPPI_OK";
+    case MPPI_E_INVALID_ARG: return "MPPI_E_INVALID_ARG";
+    case MPPI_E_NONFINITE_INPUT: return "MPPI_E_NONFINITE_INPUT";
+    case MPPI_E_ALL_NONFINITE: return "MPPI_E_ALL_NONFINITE";
+    case MPPI_E_BUDGET: return "MPPI_E_BUDGET";
+    case MPPI_E_OOM: return "MPPI_E_OOM";
+    case MPPI_E_HIP: return "MPPI_E_HIP";
+    case MPPI_E_PENDING: return "MPPI_E_PENDING";
+    case MPPI_E_CAPACITY: return "MPPI_E_CAPACITY";
+    default: return "MPPI_E_UNKNOWN";
+    }
+}
+
+const char* mppi_last_error(const mppi_ctx* ctx)
+{
+    return ctx ? ctx->last_error.c_str() : "null context";
+}
+
+mppi_status mppi_validate(const mppi_vehicle* veh, const mppi_cost* cost, const mppi_solve* solve,
+                          int32_t M)
+{
+    mppi_status s;
+    if ((s = check_vehicle(veh)) != MPPI_OK) return s;
+    if ((s = check_cost(cost)) != MPPI_OK) return s;
+    if ((s = check_solve(solve)) != MPPI_OK) return s;
+    if (M < 0 || M > MPPI_M_MAX) return MPPI_E_INVALID_ARG;
+    return MPPI_OK;
+}
+
+mppi_status mppi_create(int device, mppi_ctx** out)
+{
+    if (!out) return MPPI_E_INVALID_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return MPPI_E_INVALID_ARG;
+    mppi_ctx* ctx = new (std::nothrow) mppi_ctx();
+    if (!ctx) return MPPI_E_OOM;
+    ctx->device = device;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete ctx;
+        return MPPI_E_HIP;
+    }
+    *out = ctx;
+    return MPPI_OK;
+}
+
+mppi_status mppi_destroy(mppi_ctx* ctx)
+{
+    if (!ctx) return MPPI_E_INVALID_ARG;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    free_scratch(ctx);
+    for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->pending) (void)hipEventDestroy(e);
+    delete ctx;
+    return MPPI_OK;
+}
+
+mppi_status mppi_reserve(mppi_ctx* ctx, int32_t K, int32_t N, int32_t M)
+{
+    if (!ctx) return MPPI_E_INVALID_ARG;
+    if (K < 1 || N < 1 || N > MPPI_N_MAX || M < 0 || M > MPPI_M_MAX)
+        return fail(ctx, MPPI_E_INVALID_ARG, "reserve: size out of range");
+    if (K <= ctx->K_cap && N <= ctx->N_cap) {
+        if (M > ctx->M_cap) ctx->M_cap = M;
+        return MPPI_OK;
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    const int Kc = K > ctx->K_cap ? K : ctx->K_cap;
+    const int Nc = N > ctx->N_cap ? N : ctx->N_cap;
+    const int Mc = M > ctx->M_cap ? M : ctx->M_cap;
+    free_scratch(ctx);
+    const int ld = (Kc + 63) & ~63;   // rows start on 256-byte boundaries
+    const size_t du_bytes = sizeof(float) * (size_t)Nc * 4 * ld;
+    if (hipMalloc(&ctx->du, du_bytes) != hipSuccess || hipMalloc(&ctx->S, sizeof(float) * ld) != hipSuccess ||
+        hipMalloc(&ctx->w, sizeof(float) * ld) != hipSuccess ||
+        hipMalloc(&ctx->u_upd, sizeof(float) * 4 * (size_t)Nc) != hipSuccess ||
+        hipMalloc(&ctx->diag, sizeof(mppi_diag)) != hipSuccess) {
+        free_scratch(ctx);
+        (void)hipGetLastError();
+        return fail(ctx, MPPI_E_OOM, "reserve: device allocation failed");
+    }
+    ctx->K_cap = Kc; ctx->N_cap = Nc; ctx->M_cap = Mc; ctx->ld = ld;
+    return MPPI_OK;
+}
+
+mppi_status mppi_update(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh, const mppi_cost* cost,
+                        const mppi_solve* solve, const float* x_hat, const float* x_ref,
+                        const mppi_obstacle* obs, int32_t M, float* u_nom, float* u_apply,
+                        mppi_diag* diag)
+{
+    if (!ctx) return MPPI_E_INVALID_ARG;
+    mppi_status st = mppi_validate(veh, cost, solve, M);
+    if (st != MPPI_OK) return fail(ctx, st, "update: invalid parameters");
+    if (!x_hat || !x_ref || !u_nom || !u_apply || (M > 0 && !obs))
+        return fail(ctx, MPPI_E_INVALID_ARG, "update: null device pointer");
+    if (solve->K > ctx->K_cap || solve->N > ctx->N_cap || M > ctx->M_cap)
+        return fail(ctx, MPPI_E_CAPACITY, "update: request exceeds reserved scratch");
+    hipStream_t s = (hipStream_t)stream;
+    mppi_diag* dg = diag ? diag : ctx->diag;
+
+    RolloutArgs a = rollout_args(*veh, *cost, *solve);
+    a.x_hat = x_hat; a.x_ref = x_ref; a.obs = obs; a.M = M; a.u_nom = u_nom;
+    a.du = ctx->du; a.ld = ctx->ld; a.S = ctx->S; a.states = nullptr;
+
+    hipEvent_t ev[kEventsPerUpdate] = {};
+    if (ctx->profiling)
+        for (int i = 0; i < kEventsPerUpdate; ++i)
+            if (!(ev[i] = take_event(ctx))) return fail(ctx, MPPI_E_HIP, "update: event creation");
+    auto mark = [&](int i) -> hipError_t {
+        return ctx->profiling ? hipEventRecord(ev[i], s) : hipSuccess;
+    };
+
+    HIP_TRY(ctx, mark(0));
+    HIP_TRY(ctx, launch_rollout(a, ctx->rollout_block, s));
+    HIP_TRY(ctx, mark(1));
+    HIP_TRY(ctx, launch_weights(ctx->S, solve->K, solve->lambda, ctx->w, dg, s));
+    HIP_TRY(ctx, mark(2));
+    HIP_TRY(ctx, launch_weighted_sum(ctx->w, ctx->du, solve->K, solve->N, ctx->ld, u_nom,
+                                     ctx->u_upd, dg, s));
+    HIP_TRY(ctx, mark(3));
+    HIP_TRY(ctx, launch_apply_shift(a.mp, x_hat, ctx->u_upd, u_nom, u_apply, solve->N,
+                                    solve->u_init, dg, s));
+    HIP_TRY(ctx, mark(4));
+    if (ctx->profiling)
+        for (int i = 0; i < kEventsPerUpdate; ++i) ctx->pending.push_back(ev[i]);
+    return MPPI_OK;
+}
+
+mppi_status mppi_rollout(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh, const mppi_cost* cost,
+                         const mppi_solve* solve, const float* x_hat, const float* x_ref,
+                         const mppi_obstacle* obs, int32_t M, const float* u_nom, float* du,
+                         int32_t ld, float* S, float* states)
+{
+    if (!ctx) return MPPI_E_INVALID_ARG;
+    mppi_status st = mppi_validate(veh, cost, solve, M);
+    if (st != MPPI_OK) return fail(ctx, st, "rollout: invalid parameters");
+    if (!x_hat || !x_ref || !u_nom || !du || !S || (M > 0 && !obs) || ld < solve->K)
+        return fail(ctx, MPPI_E_INVALID_ARG, "rollout: null pointer or ld < K");
+    RolloutArgs a = rollout_args(*veh, *cost, *solve);
+    a.x_hat = x_hat; a.x_ref = x_ref; a.obs = obs; a.M = M; a.u_nom = u_nom;
+    a.du = du; a.ld = ld; a.S = S; a.states = states;
+    HIP_TRY(ctx, launch_rollout(a, ctx->rollout_block, (hipStream_t)stream));
+    return MPPI_OK;
+}
+
+mppi_status mppi_weights(mppi_ctx* ctx, void* stream, int32_t K, const float* S, float lambda,
+                         float* w, mppi_diag* diag)
+{
+    if (!ctx) return MPPI_E_INVALID_ARG;
+    if (K < 1 || !S || !w || !diag || !std::isfinite(lambda) || !(lambda > 0))
+        return fail(ctx, MPPI_E_INVALID_ARG, "weights: bad argument");
+    HIP_TRY(ctx, launch_weights(S, K, lambda, w, diag, (hipStream_t)stream));
+    return MPPI_OK;
+}
+
+mppi_status mppi_weighted_sum(mppi_ctx* ctx, void* stream, int32_t K, int32_t N, const float* w,
+                              const float* du, int32_t ld, const float* u_in, float* u_out,
+                              const mppi_diag* diag)
+{
+    if (!ctx) return MPPI_E_INVALID_ARG;
+    if (K < 1 || N < 1 || N > MPPI_N_MAX || ld < K || !w || !du || !u_in || !u_out)
+        return fail(ctx, MPPI_E_INVALID_ARG, "weighted_sum: bad argument");
+    if ((ld & 3) == 0 && ((reinterpret_cast<uintptr_t>(du) | reinterpret_cast<uintptr_t>(w)) & 15))
+        return fail(ctx, MPPI_E_INVALID_ARG, "weighted_sum: du and w must be 16-byte aligned");
+    HIP_TRY(ctx, launch_weighted_sum(w, du, K, N, ld, u_in, u_out, diag, (hipStream_t)stream));
+    return MPPI_OK;
+}
+
+mppi_status mppi_apply_shift(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh,
+                             const mppi_solve* solve, const float* x_hat, const float* u_upd,
+                             float* u_nom, float* u_apply)
+{
+    if (!ctx) return MPPI_E_INVALID_ARG;
+    mppi_status st;
+    if ((st = check_vehicle(veh)) != MPPI_OK || (st = check_solve(solve)) != MPPI_OK)
+        return fail(ctx, st, "apply_shift: invalid parameters");
+    if (!x_hat || !u_upd || !u_nom || !u_apply || u_upd == u_nom)
+        return fail(ctx, MPPI_E_INVALID_ARG, "apply_shift: null or aliased pointer");
+    HIP_TRY(ctx, launch_apply_shift(model_params(*veh, solve->dt), x_hat, u_upd, u_nom, u_apply,
+                                    solve->N, solve->u_init, nullptr, (hipStream_t)stream));
+    return MPPI_OK;
+}
+
+mppi_status mppi_noise(mppi_ctx* ctx, void* stream, const mppi_solve* solve, float* du, int32_t ld)
+{
+    if (!ctx) return MPPI_E_INVALID_ARG;
+    mppi_status st = check_solve(solve);
+    if (st != MPPI_OK) return fail(ctx, st, "noise: invalid parameters");
+    if (!du || ld < solve->K) return fail(ctx, MPPI_E_INVALID_ARG, "noise: bad argument");
+    HIP_TRY(ctx, launch_noise(noise_params(*solve), solve->K, solve->N, du, ld, (hipStream_t)stream));
+    return MPPI_OK;
+}
+
+mppi_status mppi_philox(mppi_ctx* ctx, void* stream, int32_t n, const uint32_t* ctr,
+                        const uint32_t* key, uint32_t* out)
+{
+    if (!ctx) return MPPI_E_INVALID_ARG;
+    if (n < 0 || (n > 0 && (!ctr || !key || !out)))
+        return fail(ctx, MPPI_E_INVALID_ARG, "philox: bad argument");
+    if (((reinterpret_cast<uintptr_t>(ctr) | reinterpret_cast<uintptr_t>(out)) & 15) ||
+        (reinterpret_cast<uintptr_t>(key) & 7))
+        return fail(ctx, MPPI_E_INVALID_ARG, "philox: misaligned buffer");
+    if (n == 0) return MPPI_OK;
+    HIP_TRY(ctx, launch_philox(n, ctr, key, out, (hipStream_t)stream));
+    return MPPI_OK;
+}
+
+mppi_status mppi_plant_step(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh, float dt,
+                            const float* x, const float* u, float* x_out)
+{
+    if (!ctx) return MPPI_E_INVALID_ARG;
+    mppi_status st = check_vehicle(veh);
+    if (st != MPPI_OK) return fail(ctx, st, "plant_step: invalid vehicle");
+    if (!std::isfinite(dt) || !(dt > 0) || !x || !u || !x_out)
+        return fail(ctx, MPPI_E_INVALID_ARG, "plant_step: bad argument");
+    HIP_TRY(ctx, launch_plant(model_params(*veh, dt), x, u, x_out, (hipStream_t)stream));
+    return MPPI_OK;
+}
+
+mppi_status mppi_profile_enable(mppi_ctx* ctx, int32_t on)
+{
+    if (!ctx) return MPPI_E_INVALID_ARG;
+    ctx->profiling = on != 0;
+    return MPPI_OK;
+}
+
+mppi_status mppi_profile_read(mppi_ctx* ctx, mppi_profile* out)
+{
+    if (!ctx || !out) return MPPI_E_INVALID_ARG;
+    for (size_t b = 0; b + kEventsPerUpdate <= ctx->pending.size(); b += kEventsPerUpdate) {
+        hipEvent_t* e = &ctx->pending[b];
+        HIP_TRY(ctx, hipEventSynchronize(e[kEventsPerUpdate - 1]));
+        float t[4];
+        for (int i = 0; i < 4; ++i) HIP_TRY(ctx, hipEventElapsedTime(&t[i], e[i], e[i + 1]));
+        ctx->acc.updates += 1;
+        ctx->acc.rollout_ms += t[0];
+        ctx->acc.weights_ms += t[1];
+        ctx->acc.reduce_ms += t[2];
+        ctx->acc.apply_ms += t[3];
+    }
+    for (hipEvent_t e : ctx->pending) ctx->pool.push_back(e);
+    ctx->pending.clear();
+    *out = ctx->acc;
+    ctx->acc = mppi_profile{};
+    return MPPI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,46 @@
+// Internal interface between the C ABI (api.hip) and the kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/mppi.h"
+#include "model.h"
+
+namespace mppi {
+
+constexpr int kWeightsThreads = 1024;
+constexpr int kSumThreads = 256;
+
+// Arguments of the rollout kernel, passed by value in the kernel-argument segment.
+struct RolloutArgs {
+    ModelParams mp;
+    CostParams cp;
+    NoiseParams np;
+    const float* x_hat;          // 17
+    const float* x_ref;          // (N+1) x 13
+    const mppi_obstacle* obs;    // M
+    int M;
+    const float* u_nom;          // N x 4
+    int K, N;
+    float* du;                   // [N][4][ld]
+    int ld;
+    float* S;                    // K
+    float* states;               // [N+1][17][ld] or nullptr
+};
+
+hipError_t launch_rollout(const RolloutArgs& a, int block, hipStream_t stream);
+hipError_t launch_weights(const float* S, int K, float lambda, float* w, mppi_diag* diag,
+                          hipStream_t stream);
+hipError_t launch_weighted_sum(const float* w, const float* du, int K, int N, int ld,
+                               const float* u_in, float* u_out, const mppi_diag* diag,
+                               hipStream_t stream);
+hipError_t launch_apply_shift(const ModelParams& P, const float* x_hat, const float* u_upd,
+                              float* u_nom, float* u_apply, int N, const float u_init[4],
+                              const mppi_diag* diag, hipStream_t stream);
+hipError_t launch_plant(const ModelParams& P, const float* x, const float* u, float* x_out,
+                        hipStream_t stream);
+hipError_t launch_noise(const NoiseParams& np, int K, int N, float* du, int ld, hipStream_t stream);
+hipError_t launch_philox(int n, const uint32_t* ctr, const uint32_t* key, uint32_t* out,
+                         hipStream_t stream);
+
+}  // namespace mppi

@@ -1,0 +1,406 @@
+// MPPI kernels for gfx950 (wave64, CDNA4).
+//
+//   rollout_kernel      one lane per sample: in-register Philox noise, rate
+//                       controller, RK4 of the 17-value state, tracking and
+//                       obstacle cost (obstacles staged in LDS)        Eqs. (2)-(3)
+//   weights_kernel      one workgroup: wave-shuffle min, compensated
+//                       sum of exp(-(S - rho)/lambda), normalisation   Eq. (4)
+//   weighted_sum_kernel one workgroup per (j, d) row of delta_u [N][4][ld]:
+//                       coalesced float4 GEMV against the weights       Eq. (5)
+//   apply_shift_kernel  u_apply and the shifted warm start              Algorithm 1
+//   plant_kernel        one noise-free model step (closed-loop plant)
+//   noise_kernel, philox_kernel   the rollout's noise on its own (checks)
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+
+#include "kernels.h"
+
+namespace mppi {
+
+// ---------------------------------------------------------------------------
+// G1: rollouts and costs
+// ---------------------------------------------------------------------------
+
+template <bool kDump>
+__global__ __launch_bounds__(256) void rollout_kernel(RolloutArgs a)
+{
+    extern __shared__ float4 obs_lds[];   // 2 x M float4
+    const float phx = a.x_hat[0], phy = a.x_hat[1], phz = a.x_hat[2];
+
+    // Stage the obstacle list once per workgroup, centred on x_hat's position:
+    // the rollouts integrate positions relative to p_hat, which keeps binary32
+    // rounding at the scale of the excursion rather than of the world frame.
+    for (int i = threadIdx.x; i < a.M; i += blockDim.x) {
+        const mppi_obstacle o = a.obs[i];
+        const float R = o.r + a.cp.margin;
+        obs_lds[2 * i] = make_float4(o.c[0] - phx, o.c[1] - phy, o.c[2] - phz,
+                                     o.type == MPPI_VCYLINDER ? 0.0f : 1.0f);
+        obs_lds[2 * i + 1] = make_float4(o.r * o.r, R * R, R, 0.0f);
+    }
+    __syncthreads();
+
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.K) return;
+    const size_t ld = (size_t)a.ld;
+
+    State x;
+    x.px = 0.0f; x.py = 0.0f; x.pz = 0.0f;
+    x.qw = a.x_hat[3]; x.qx = a.x_hat[4]; x.qy = a.x_hat[5]; x.qz = a.x_hat[6];
+    x.vx = a.x_hat[7]; x.vy = a.x_hat[8]; x.vz = a.x_hat[9];
+    x.wx = a.x_hat[10]; x.wy = a.x_hat[11]; x.wz = a.x_hat[12];
+    x.T0 = a.x_hat[13]; x.T1 = a.x_hat[14]; x.T2 = a.x_hat[15]; x.T3 = a.x_hat[16];
+
+    if (kDump) {   // trajectories [N+1][17][ld], positions back in the world frame
+        const float vals[17] = {x.px + phx, x.py + phy, x.pz + phz, x.qw, x.qx, x.qy, x.qz,
+                                x.vx, x.vy, x.vz, x.wx, x.wy, x.wz, x.T0, x.T1, x.T2, x.T3};
+#pragma unroll
+        for (int i = 0; i < 17; ++i) a.states[(size_t)i * ld + k] = vals[i];
+    }
+
+    KahanSum S;
+    // state j = 0 (the estimate itself) is scored like every other state (Eq. (17))
+    S.add(tracking_cost(a.cp, x, a.x_ref[0] - phx, a.x_ref[1] - phy, a.x_ref[2] - phz, a.x_ref) +
+          obstacle_cost(a.cp, x.px, x.py, x.pz, obs_lds, a.M));
+
+    float up[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int j = 0; j < a.N; ++j) {
+        float du[4], u[4];
+        draw_noise(a.np, (uint32_t)k, (uint32_t)j, du);
+        float* dst = a.du + (size_t)(4 * j) * ld + k;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            dst[(size_t)d * ld] = du[d];
+            u[d] = a.u_nom[4 * j + d] + du[d];          // Eq. (2): u = u_nom + delta_u
+        }
+        // input and input-change terms of Eq. (16)
+        float cu = 0.0f;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) cu = fmaf(a.cp.R[d] * u[d], u[d], cu);
+        if (j > 0) {
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const float e = u[d] - up[d];
+                cu = fmaf(a.cp.Rd[d] * e, e, cu);
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) up[d] = u[d];
+
+        float Tc[4];
+        rate_controller(a.mp, x.wx, x.wy, x.wz, u, Tc);
+        rk4_step(a.mp, x, Tc);
+
+        const float* ref = a.x_ref + (size_t)13 * (j + 1);
+        const float cx = tracking_cost(a.cp, x, ref[0] - phx, ref[1] - phy, ref[2] - phz, ref) +
+                         obstacle_cost(a.cp, x.px, x.py, x.pz, obs_lds, a.M);
+        S.add(cu + cx);
+
+        if (kDump) {
+            const float vals[17] = {x.px + phx, x.py + phy, x.pz + phz, x.qw, x.qx, x.qy, x.qz,
+                                    x.vx, x.vy, x.vz, x.wx, x.wy, x.wz, x.T0, x.T1, x.T2, x.T3};
+            float* st = a.states + (size_t)17 * (j + 1) * ld + k;
+#pragma unroll
+            for (int i = 0; i < 17; ++i) st[(size_t)i * ld] = vals[i];
+        }
+    }
+    a.S[k] = S.s;
+}
+
+// ---------------------------------------------------------------------------
+// Block reductions (wave64 shuffles, then LDS across waves)
+// ---------------------------------------------------------------------------
+
+// Lexicographic (value, index) minimum; NaN never wins.
+__device__ __forceinline__ void argmin_merge(float& v, int& i, float v2, int i2)
+{
+    if (v2 < v || (v2 == v && i2 < i)) { v = v2; i = i2; }
+}
+
+// Error-free sum of two compensated pairs (Knuth two-sum).
+__device__ __forceinline__ void twosum_merge(float& s, float& c, float s2, float c2)
+{
+    const float t = s + s2;
+    const float bp = t - s;
+    const float e = (s - (t - bp)) + (s2 - bp);
+    s = t;
+    c = c + c2 + e;
+}
+
+// ---------------------------------------------------------------------------
+// G2: softmin weights
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kWeightsThreads) void weights_kernel(const float* __restrict__ S, int K,
+                                                                 float lambda, float* __restrict__ w,
+                                                                 mppi_diag* __restrict__ diag)
+{
+    __shared__ float sh_v[kWeightsThreads / 64];
+    __shared__ int sh_i[kWeightsThreads / 64], sh_n[kWeightsThreads / 64];
+    __shared__ float sh_s[kWeightsThreads / 64], sh_c[kWeightsThreads / 64], sh_q[kWeightsThreads / 64];
+    __shared__ float bc_rho;
+    __shared__ int bc_n;
+    __shared__ float bc_eta;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+
+    // rho = min over finite costs, its first index, and the finite count
+    float mv = INFINITY;
+    int mi = INT_MAX, nf = 0;
+    for (int k = tid; k < K; k += blockDim.x) {
+        const float s = S[k];
+        if (isfinite(s)) {
+            ++nf;
+            if (s < mv) { mv = s; mi = k; }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const float v2 = __shfl_xor(mv, off);
+        const int i2 = __shfl_xor(mi, off);
+        argmin_merge(mv, mi, v2, i2);
+        nf += __shfl_xor(nf, off);
+    }
+    if (lane == 0) { sh_v[wv] = mv; sh_i[wv] = mi; sh_n[wv] = nf; }
+    __syncthreads();
+    if (tid == 0) {
+        float v = sh_v[0];
+        int i = sh_i[0], n = sh_n[0];
+        for (int q = 1; q < nw; ++q) { argmin_merge(v, i, sh_v[q], sh_i[q]); n += sh_n[q]; }
+        bc_rho = v; bc_n = n;
+        diag->rho = v; diag->argmin = n > 0 ? i : -1; diag->n_finite = n;
+    }
+    __syncthreads();
+    const float rho = bc_rho;
+    if (bc_n == 0) {
+        for (int k = tid; k < K; k += blockDim.x) w[k] = 0.0f;
+        if (tid == 0) {
+            diag->eta = 0.0f; diag->ess = 0.0f; diag->status = MPPI_E_ALL_NONFINITE;
+        }
+        return;
+    }
+
+    // e_k = exp(-(S_k - rho) / lambda) = 2^((rho - S_k) log2(e) / lambda); eta = sum_k e_k
+    const float scale = 1.44269504089f / lambda;
+    float es = 0.0f, ec = 0.0f, q2 = 0.0f;
+    for (int k = tid; k < K; k += blockDim.x) {
+        const float s = S[k];
+        const float e = isfinite(s) ? __builtin_amdgcn_exp2f((rho - s) * scale) : 0.0f;
+        w[k] = e;
+        const float y = e - ec, t = es + y;          // Kahan
+        ec = (t - es) - y;
+        es = t;
+        q2 = fmaf(e, e, q2);
+    }
+    ec = -ec;   // pair (es, ec) with es + ec the compensated value
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const float s2 = __shfl_xor(es, off), c2 = __shfl_xor(ec, off);
+        twosum_merge(es, ec, s2, c2);
+        q2 += __shfl_xor(q2, off);
+    }
+    if (lane == 0) { sh_s[wv] = es; sh_c[wv] = ec; sh_q[wv] = q2; }
+    __syncthreads();
+    if (tid == 0) {
+        float s = sh_s[0], c = sh_c[0], q = sh_q[0];
+        for (int i = 1; i < nw; ++i) { twosum_merge(s, c, sh_s[i], sh_c[i]); q += sh_q[i]; }
+        const float eta = s + c;
+        bc_eta = eta;
+        diag->eta = eta;
+        diag->ess = eta * eta / q;
+        diag->status = MPPI_OK;
+    }
+    __syncthreads();
+    const float inv_eta = 1.0f / bc_eta;
+    for (int k = tid; k < K; k += blockDim.x) w[k] *= inv_eta;
+}
+
+// ---------------------------------------------------------------------------
+// G3: weighted sum of the perturbations, one workgroup per (j, d) row
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kSumThreads) void weighted_sum_kernel(
+    const float* __restrict__ w, const float* __restrict__ du, int K, int ld,
+    const float* __restrict__ u_in, float* __restrict__ u_out, const mppi_diag* __restrict__ diag)
+{
+    __shared__ float sh[kSumThreads / 64];
+    const int row = blockIdx.x, tid = threadIdx.x;
+    const float* src = du + (size_t)row * ld;
+    float acc = 0.0f;
+    if ((ld & 3) == 0) {
+        const int K4 = K >> 2;
+        const float4* s4 = reinterpret_cast<const float4*>(src);
+        const float4* w4 = reinterpret_cast<const float4*>(w);
+        for (int i = tid; i < K4; i += blockDim.x) {
+            const float4 a = s4[i], b = w4[i];
+            acc = fmaf(a.x, b.x, acc);
+            acc = fmaf(a.y, b.y, acc);
+            acc = fmaf(a.z, b.z, acc);
+            acc = fmaf(a.w, b.w, acc);
+        }
+        for (int k = 4 * K4 + tid; k < K; k += blockDim.x) acc = fmaf(src[k], w[k], acc);
+    } else {
+        for (int k = tid; k < K; k += blockDim.x) acc = fmaf(src[k], w[k], acc);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((tid & 63) == 0) sh[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        float t = 0.0f;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+        const bool ok = diag == nullptr || diag->status == MPPI_OK;
+        u_out[row] = ok ? u_in[row] + t : u_in[row];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// G4: apply and shift
+// ---------------------------------------------------------------------------
+
+__device__ void feasible_input(const ModelParams& P, const float* x, const float* u, float* out)
+{
+    // Eqs. (12)-(15): clipped thrusts -> [F_clip; tau_clip] -> omega_clip
+    float Tc[4];
+    const float uu[4] = {u[0], u[1], u[2], u[3]};
+    rate_controller(P, x[10], x[11], x[12], uu, Tc);
+    const float s01 = Tc[0] + Tc[1], s23 = Tc[2] + Tc[3], d10 = Tc[1] - Tc[0], d23 = Tc[2] - Tc[3];
+    const float F = s01 + s23;
+    const float tau[3] = {P.s * (d10 + d23), P.s * (d10 - d23), P.c * (s23 - s01)};
+    const float gyr[3] = {P.G[0] * x[11] * x[12], P.G[1] * x[12] * x[10], P.G[2] * x[10] * x[11]};
+    const float lim[3] = {P.w_xy_max, P.w_xy_max, P.w_z_max};
+    out[0] = F;
+    for (int i = 0; i < 3; ++i) {
+        float wc = fmaf((tau[i] - gyr[i]) * P.J_inv[i], P.dt, x[10 + i]);
+        if (lim[i] > 0.0f) wc = clampf(wc, -lim[i], lim[i]);
+        out[1 + i] = wc;
+    }
+}
+
+__global__ void apply_shift_kernel(ModelParams P, const float* __restrict__ x_hat,
+                                   const float* __restrict__ u_upd, float* __restrict__ u_nom,
+                                   float* __restrict__ u_apply, int N, float4 u_init,
+                                   const mppi_diag* __restrict__ diag)
+{
+    const bool ok = diag == nullptr || diag->status == MPPI_OK;
+    if (threadIdx.x == 0) {
+        for (int d = 0; d < 4; ++d) u_apply[d] = u_upd[d];
+        feasible_input(P, x_hat, u_upd, u_apply + 4);
+    }
+    if (!ok) return;   // all costs non-finite: keep the warm start as it was
+    const float init[4] = {u_init.x, u_init.y, u_init.z, u_init.w};
+    for (int i = threadIdx.x; i < 4 * N; i += blockDim.x)
+        u_nom[i] = i < 4 * (N - 1) ? u_upd[i + 4] : init[i & 3];
+}
+
+// ---------------------------------------------------------------------------
+// Plant, noise and Philox kernels
+// ---------------------------------------------------------------------------
+
+__global__ void plant_kernel(ModelParams P, const float* __restrict__ x_in,
+                             const float* __restrict__ u_in, float* __restrict__ x_out)
+{
+    if (threadIdx.x != 0) return;
+    State x;
+    x.px = x_in[0]; x.py = x_in[1]; x.pz = x_in[2];
+    x.qw = x_in[3]; x.qx = x_in[4]; x.qy = x_in[5]; x.qz = x_in[6];
+    x.vx = x_in[7]; x.vy = x_in[8]; x.vz = x_in[9];
+    x.wx = x_in[10]; x.wy = x_in[11]; x.wz = x_in[12];
+    x.T0 = x_in[13]; x.T1 = x_in[14]; x.T2 = x_in[15]; x.T3 = x_in[16];
+    const float u[4] = {u_in[0], u_in[1], u_in[2], u_in[3]};
+    float Tc[4];
+    rate_controller(P, x.wx, x.wy, x.wz, u, Tc);
+    rk4_step(P, x, Tc);
+    const float out[17] = {x.px, x.py, x.pz, x.qw, x.qx, x.qy, x.qz, x.vx, x.vy, x.vz,
+                           x.wx, x.wy, x.wz, x.T0, x.T1, x.T2, x.T3};
+    for (int i = 0; i < 17; ++i) x_out[i] = out[i];
+}
+
+__global__ void noise_kernel(NoiseParams np, int K, int N, float* __restrict__ du, int ld)
+{
+    const size_t total = (size_t)K * N;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(i % K), j = (int)(i / K);
+        float v[4];
+        draw_noise(np, (uint32_t)k, (uint32_t)j, v);
+        for (int d = 0; d < 4; ++d) du[(size_t)(4 * j + d) * ld + k] = v[d];
+    }
+}
+
+__global__ void philox_kernel(int n, const uint4* __restrict__ ctr, const uint2* __restrict__ key,
+                              uint4* __restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = philox4x32_10(ctr[i], key[i].x, key[i].y);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_rollout(const RolloutArgs& a, int block, hipStream_t stream)
+{
+    const int grid = (a.K + block - 1) / block;
+    const size_t lds = sizeof(float4) * 2 * (size_t)a.M;
+    if (a.states)
+        hipLaunchKernelGGL(rollout_kernel<true>, dim3(grid), dim3(block), lds, stream, a);
+    else
+        hipLaunchKernelGGL(rollout_kernel<false>, dim3(grid), dim3(block), lds, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_weights(const float* S, int K, float lambda, float* w, mppi_diag* diag,
+                          hipStream_t stream)
+{
+    hipLaunchKernelGGL(weights_kernel, dim3(1), dim3(kWeightsThreads), 0, stream, S, K, lambda, w,
+                       diag);
+    return hipGetLastError();
+}
+
+hipError_t launch_weighted_sum(const float* w, const float* du, int K, int N, int ld,
+                               const float* u_in, float* u_out, const mppi_diag* diag,
+                               hipStream_t stream)
+{
+    hipLaunchKernelGGL(weighted_sum_kernel, dim3(4 * N), dim3(kSumThreads), 0, stream, w, du, K,
+                       ld, u_in, u_out, diag);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_shift(const ModelParams& P, const float* x_hat, const float* u_upd,
+                              float* u_nom, float* u_apply, int N, const float u_init[4],
+                              const mppi_diag* diag, hipStream_t stream)
+{
+    const float4 ui = make_float4(u_init[0], u_init[1], u_init[2], u_init[3]);
+    hipLaunchKernelGGL(apply_shift_kernel, dim3(1), dim3(256), 0, stream, P, x_hat, u_upd, u_nom,
+                       u_apply, N, ui, diag);
+    return hipGetLastError();
+}
+
+hipError_t launch_plant(const ModelParams& P, const float* x, const float* u, float* x_out,
+                        hipStream_t stream)
+{
+    hipLaunchKernelGGL(plant_kernel, dim3(1), dim3(64), 0, stream, P, x, u, x_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_noise(const NoiseParams& np, int K, int N, float* du, int ld, hipStream_t stream)
+{
+    const size_t total = (size_t)K * N;
+    const int block = 256;
+    const int grid = (int)((total + block - 1) / block < 65536 ? (total + block - 1) / block : 65536);
+    hipLaunchKernelGGL(noise_kernel, dim3(grid), dim3(block), 0, stream, np, K, N, du, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(int n, const uint32_t* ctr, const uint32_t* key, uint32_t* out,
+                         hipStream_t stream)
+{
+    const int block = 256;
+    hipLaunchKernelGGL(philox_kernel, dim3((n + block - 1) / block), dim3(block), 0, stream, n,
+                       reinterpret_cast<const uint4*>(ctr), reinterpret_cast<const uint2*>(key),
+                       reinterpret_cast<uint4*>(out));
+    return hipGetLastError();
+}
+
+}  // namespace mppi

@@ -1,0 +1,248 @@
+// Device-side quadrotor model, noise and cost for the MPPI rollouts (gfx950).
+//
+// Everything here runs per lane in binary32 registers:
+//   - counter-based Philox4x32-10 (Salmon et al., SC'11) and Box-Muller, giving
+//     the perturbations delta_u ~ N(0, diag(sigma^2)) of Sec. III-A, Eq. (2);
+//   - the body-rate controller, allocation and rotor saturation of Sec. III-B,
+//     Eqs. (8)-(12), evaluated once per step and held over the step;
+//   - the rigid-body dynamics of Eq. (6) driven by the rotor thrusts through the
+//     allocation matrix (Eq. (13)), with an optional first-order rotor lag;
+//   - one classic RK4 step followed by quaternion renormalisation (Eq. (2));
+//   - the per-state tracking cost of Eq. (18) with the quaternion distance of
+//     Eq. (21), and the obstacle term of Eq. (22) with a quadratic margin.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mppi {
+
+// Vehicle constants, derived on the host from mppi_vehicle for one call.
+struct ModelParams {
+    float m_inv, g;
+    float J[3], J_inv[3];
+    // omega x (J omega) = (G0 wy wz, G1 wz wx, G2 wx wy), G = (Jz-Jy, Jx-Jz, Jy-Jx)
+    float G[3];
+    // Gamma rows 1..3 are s(-1,1,1,-1), s(-1,1,-1,1), c(-1,-1,1,1) with s = l/sqrt(2);
+    // Gamma's rows are orthogonal, so Gamma^-1 = Gamma^T diag(1/4, 1/(4s^2), 1/(4s^2), 1/(4c^2)).
+    float s, c, inv_4s, inv_4c;
+    float T_min, T_max;
+    float tau_inv;   // 1 / tau_m (rotor lag); unused when lag == 0
+    int lag;         // 0: thrusts equal the clipped command (Eq. (13))
+    float k_w;       // rate-controller gain (1/dt in Eq. (8))
+    float dt;
+    float w_xy_max, w_z_max;
+};
+
+struct CostParams {
+    float c_p, c_v, c_q, c_w;
+    float R[4], Rd[4];
+    float margin, w_obs, c_col;
+};
+
+struct NoiseParams {
+    float sigma[4];
+    uint32_t key0, key1;    // seed low word, vehicle id
+    uint32_t t, seed_hi;    // counter words 2 and 3
+};
+
+// 17 state values held in registers.
+struct State {
+    float px, py, pz;
+    float qw, qx, qy, qz;
+    float vx, vy, vz;
+    float wx, wy, wz;
+    float T0, T1, T2, T3;
+};
+
+// ---------------------------------------------------------------------------
+// Noise
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// ((w >> 9) + 0.5) * 2^-23 in (0, 1): the bit pattern 1.m minus (1 - 2^-24) is
+// exact because the result (2m + 1) 2^-24 is representable.
+__device__ __forceinline__ float unit_uniform(uint32_t w)
+{
+    return __uint_as_float((w >> 9) | 0x3F800000u) - 0.99999994f;
+}
+
+// delta_u for sample k, step j: Philox counter (k, j, t, seed_hi), Box-Muller on
+// (u0, u1) and (u2, u3).  v_sin/v_cos take revolutions, so sin(2 pi u) is one op.
+__device__ __forceinline__ void draw_noise(const NoiseParams& np, uint32_t k, uint32_t j,
+                                           float du[4])
+{
+    const uint4 w = philox4x32_10(make_uint4(k, j, np.t, np.seed_hi), np.key0, np.key1);
+    const float u0 = unit_uniform(w.x), u1 = unit_uniform(w.y);
+    const float u2 = unit_uniform(w.z), u3 = unit_uniform(w.w);
+    const float neg2ln2 = -1.38629436112f;   // -2 ln 2: ln u = ln 2 * log2 u
+    const float r0 = __builtin_amdgcn_sqrtf(neg2ln2 * __builtin_amdgcn_logf(u0));
+    const float r1 = __builtin_amdgcn_sqrtf(neg2ln2 * __builtin_amdgcn_logf(u2));
+    du[0] = np.sigma[0] * (r0 * __builtin_amdgcn_cosf(u1));
+    du[1] = np.sigma[1] * (r0 * __builtin_amdgcn_sinf(u1));
+    du[2] = np.sigma[2] * (r1 * __builtin_amdgcn_cosf(u3));
+    du[3] = np.sigma[3] * (r1 * __builtin_amdgcn_sinf(u3));
+}
+
+// ---------------------------------------------------------------------------
+// Controller and allocation (Eqs. (8)-(12))
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float clampf(float v, float lo, float hi)
+{
+    return fminf(fmaxf(v, lo), hi);
+}
+
+// u = [F_t, omega_d]; returns the clipped rotor command.
+__device__ __forceinline__ void rate_controller(const ModelParams& P, float wx, float wy, float wz,
+                                                const float u[4], float Tc[4])
+{
+    // Eq. (8): omega_dot_d = k_w (omega_d - omega); Eq. (9): tau_d = J omega_dot_d + omega x J omega
+    const float tx = fmaf(P.J[0], P.k_w * (u[1] - wx), P.G[0] * (wy * wz));
+    const float ty = fmaf(P.J[1], P.k_w * (u[2] - wy), P.G[1] * (wz * wx));
+    const float tz = fmaf(P.J[2], P.k_w * (u[3] - wz), P.G[2] * (wx * wy));
+    // Eq. (10) with Gamma^-1 = Gamma^T D^-1
+    const float a0 = 0.25f * u[0], a1 = tx * P.inv_4s, a2 = ty * P.inv_4s, a3 = tz * P.inv_4c;
+    const float p = a0 - a3, m = a0 + a3;
+    Tc[0] = clampf(p - a1 - a2, P.T_min, P.T_max);   // Eq. (12)
+    Tc[1] = clampf(p + a1 + a2, P.T_min, P.T_max);
+    Tc[2] = clampf(m + a1 - a2, P.T_min, P.T_max);
+    Tc[3] = clampf(m - a1 + a2, P.T_min, P.T_max);
+}
+
+// ---------------------------------------------------------------------------
+// Dynamics (Eq. (6)) and RK4 (Eq. (2))
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void derivative(const ModelParams& P, const State& x, const float Tc[4],
+                                           State& d)
+{
+    const float T0 = P.lag ? x.T0 : Tc[0], T1 = P.lag ? x.T1 : Tc[1];
+    const float T2 = P.lag ? x.T2 : Tc[2], T3 = P.lag ? x.T3 : Tc[3];
+    // Eq. (13): [F; tau] = Gamma T
+    const float s01 = T0 + T1, s23 = T2 + T3, d10 = T1 - T0, d23 = T2 - T3;
+    const float F = s01 + s23;
+    const float tx = P.s * (d10 + d23), ty = P.s * (d10 - d23), tz = P.c * (s23 - s01);
+    // p' = v
+    d.px = x.vx; d.py = x.vy; d.pz = x.vz;
+    // q' = 1/2 q (x) [0, omega]
+    const float hx = 0.5f * x.wx, hy = 0.5f * x.wy, hz = 0.5f * x.wz;
+    d.qw = -(x.qx * hx + x.qy * hy + x.qz * hz);
+    d.qx = x.qw * hx + x.qy * hz - x.qz * hy;
+    d.qy = x.qw * hy - x.qx * hz + x.qz * hx;
+    d.qz = x.qw * hz + x.qx * hy - x.qy * hx;
+    // v' = R(q) [0, 0, F] / m + [0, 0, -g]; third column of R(q)
+    const float fm = F * P.m_inv, f2 = fm + fm;
+    d.vx = f2 * (x.qx * x.qz + x.qw * x.qy);
+    d.vy = f2 * (x.qy * x.qz - x.qw * x.qx);
+    d.vz = fm - f2 * (x.qx * x.qx + x.qy * x.qy) - P.g;
+    // omega' = J^-1 (tau - omega x J omega)
+    d.wx = (tx - P.G[0] * (x.wy * x.wz)) * P.J_inv[0];
+    d.wy = (ty - P.G[1] * (x.wz * x.wx)) * P.J_inv[1];
+    d.wz = (tz - P.G[2] * (x.wx * x.wy)) * P.J_inv[2];
+    // rotor lag T' = (T_cmd - T) / tau_m
+    d.T0 = (Tc[0] - x.T0) * P.tau_inv;
+    d.T1 = (Tc[1] - x.T1) * P.tau_inv;
+    d.T2 = (Tc[2] - x.T2) * P.tau_inv;
+    d.T3 = (Tc[3] - x.T3) * P.tau_inv;
+}
+
+#define MPPI_STATE_FIELDS(X) \
+    X(px) X(py) X(pz) X(qw) X(qx) X(qy) X(qz) X(vx) X(vy) X(vz) X(wx) X(wy) X(wz) \
+    X(T0) X(T1) X(T2) X(T3)
+
+// One step x <- x + f_RK4(x, Tc, dt) with the command held, then q <- q / |q|.
+__device__ __forceinline__ void rk4_step(const ModelParams& P, State& x, const float Tc[4])
+{
+    const float h = P.dt, h2 = 0.5f * P.dt, h6 = P.dt * (1.0f / 6.0f);
+    State k, xs, acc;
+    derivative(P, x, Tc, k);                                     // k1
+#define STAGE1(f) acc.f = k.f; xs.f = fmaf(h2, k.f, x.f);
+    MPPI_STATE_FIELDS(STAGE1)
+#undef STAGE1
+    derivative(P, xs, Tc, k);                                    // k2
+#define STAGE2(f) acc.f = fmaf(2.0f, k.f, acc.f); xs.f = fmaf(h2, k.f, x.f);
+    MPPI_STATE_FIELDS(STAGE2)
+#undef STAGE2
+    derivative(P, xs, Tc, k);                                    // k3
+#define STAGE3(f) acc.f = fmaf(2.0f, k.f, acc.f); xs.f = fmaf(h, k.f, x.f);
+    MPPI_STATE_FIELDS(STAGE3)
+#undef STAGE3
+    derivative(P, xs, Tc, k);                                    // k4
+#define STAGE4(f) x.f = fmaf(h6, acc.f + k.f, x.f);
+    MPPI_STATE_FIELDS(STAGE4)
+#undef STAGE4
+    const float n2 = x.qw * x.qw + x.qx * x.qx + x.qy * x.qy + x.qz * x.qz;
+    const float inv = __builtin_amdgcn_rsqf(n2);
+    x.qw *= inv; x.qx *= inv; x.qy *= inv; x.qz *= inv;
+    if (!P.lag) { x.T0 = Tc[0]; x.T1 = Tc[1]; x.T2 = Tc[2]; x.T3 = Tc[3]; }
+}
+
+// ---------------------------------------------------------------------------
+// Cost (Eqs. (16)-(22))
+// ---------------------------------------------------------------------------
+
+// rho_ref (Eq. (18)) for a state against a reference row [p, q, v, omega]; the
+// reference position is given relative to the frame origin of the state.
+__device__ __forceinline__ float tracking_cost(const CostParams& C, const State& x,
+                                               float rpx, float rpy, float rpz, const float* ref)
+{
+    const float dx = x.px - rpx, dy = x.py - rpy, dz = x.pz - rpz;
+    const float ip = x.qw * ref[3] + x.qx * ref[4] + x.qy * ref[5] + x.qz * ref[6];
+    const float dq = fmaf(-ip, ip, 1.0f);                        // Eq. (21)
+    const float ex = x.vx - ref[7], ey = x.vy - ref[8], ez = x.vz - ref[9];
+    const float ox = x.wx - ref[10], oy = x.wy - ref[11], oz = x.wz - ref[12];
+    float c = C.c_p * (dx * dx + dy * dy + dz * dz);
+    c = fmaf(C.c_q, dq * dq, c);
+    c = fmaf(C.c_v, ex * ex + ey * ey + ez * ez, c);
+    c = fmaf(C.c_w, ox * ox + oy * oy + oz * oz, c);
+    return c;
+}
+
+// Obstacles staged in LDS as two float4 per obstacle:
+//   a = (cx, cy, cz, zmask)  centre relative to the frame origin; zmask 0 for a
+//                            vertical cylinder (ignore z), 1 for a sphere
+//   b = (r^2, (r + margin)^2, r + margin, 0)
+__device__ __forceinline__ float obstacle_cost(const CostParams& C, float px, float py, float pz,
+                                               const float4* __restrict__ obs, int M)
+{
+    bool hit = false;
+    float pen = 0.0f;
+    for (int i = 0; i < M; ++i) {
+        const float4 a = obs[2 * i], b = obs[2 * i + 1];
+        const float dx = px - a.x, dy = py - a.y, dz = (pz - a.z) * a.w;
+        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        hit |= (d2 < b.x);
+        if (d2 < b.y) {
+            const float gap = b.z - __builtin_amdgcn_sqrtf(d2);
+            pen = fmaf(gap, gap, pen);
+        }
+    }
+    return fmaf(C.w_obs, pen, hit ? C.c_col : 0.0f);
+}
+
+// Kahan-compensated accumulation of the rollout cost.
+struct KahanSum {
+    float s = 0.0f, c = 0.0f;
+    __device__ __forceinline__ void add(float v)
+    {
+        const float y = v - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+};
+
+}  // namespace mppi

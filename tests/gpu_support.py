@@ -1,0 +1,74 @@
+"""Helpers shared by the GPU parity tests: device copies of a scenario, the
+binary32-rounded inputs the oracle is given, and the relative-error measure.
+
+Relative error: |gpu - oracle| / max(|oracle|, floor) with floors 1 m (position),
+1 (quaternion), 1 m/s (velocity), 1 rad/s (body rate), 1 N (thrust), sigma (noise
+and controls) -- the scale of each quantity, so that values near zero are not held
+to a relative bound they cannot meet in binary32.
+"""
+import numpy as np
+import torch
+
+TOL = 1e-4
+STATE_FLOOR = np.array([1.0] * 17)
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def f32_params(d: dict) -> dict:
+    """Round every number of a parameter dict to binary32, as the device sees it."""
+    out = {}
+    for k, v in d.items():
+        if isinstance(v, (list, tuple, np.ndarray)):
+            out[k] = tuple(float(np.float32(x)) for x in np.asarray(v).ravel())
+        elif isinstance(v, float):
+            out[k] = float(np.float32(v))
+        else:
+            out[k] = v
+    return out
+
+
+def rel_err(gpu, ref, floor):
+    gpu, ref = np.asarray(gpu, dtype=np.float64), np.asarray(ref, dtype=np.float64)
+    return np.abs(gpu - ref) / np.maximum(np.abs(ref), floor)
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+class DeviceProblem:
+    """Device-resident inputs of one update of a scenario, and the same inputs
+    rounded to binary32 for the oracle."""
+
+    def __init__(self, lib, sc, t=0, x_hat=None, u_nom=None, solve=None):
+        self.sc = sc
+        self.solve = dict(sc.solve(t) if solve is None else solve)
+        self.N, self.K, self.M = self.solve["N"], self.solve["K"], sc.M
+        x_hat = sc.x0 if x_hat is None else x_hat
+        u_nom = sc.u_nom0()[: self.N] if u_nom is None else u_nom
+        x_ref = sc.ref.rows(t * sc.dt, self.N, sc.dt)
+        self.x_hat, self.u_nom, self.x_ref = dev(x_hat), dev(u_nom), dev(x_ref)
+        self.obs = lib.obstacles_to_device(sc.obstacles)
+        # what the oracle is given: the binary32 values the device holds
+        self.o_x_hat, self.o_u_nom, self.o_x_ref = f32(x_hat), f32(u_nom), f32(x_ref)
+        self.o_obs = sc.obstacles.copy()
+        self.o_obs[:, 1:] = f32(self.o_obs[:, 1:])
+        self.o_veh, self.o_cost = f32_params(sc.veh), f32_params(sc.cost)
+        self.o_solve = f32_params(self.solve)
+
+
+def exempt_straddles(states, obstacles, delta=1e-3):
+    """Samples with a state within delta of an obstacle surface: there the collision
+    indicator may legitimately differ between binary32 and binary64 trajectories."""
+    if obstacles.shape[0] == 0:
+        return np.zeros(states.shape[0], dtype=bool)
+    p = states[:, :, None, 0:3]                      # [n, N+1, 1, 3]
+    c = obstacles[None, None, :, 1:4]
+    d = p - c
+    zmask = (obstacles[:, 0] == 0).astype(np.float64)[None, None, :]
+    dist = np.sqrt(d[..., 0] ** 2 + d[..., 1] ** 2 + (d[..., 2] * zmask) ** 2)
+    near = np.abs(dist - obstacles[None, None, :, 4]) < delta
+    return near.any(axis=(1, 2))

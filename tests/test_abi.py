@@ -1,0 +1,124 @@
+"""The C ABI boundary, checked on the host (no GPU): the library loads, exports every
+entry point include/mppi.h declares, its structs have the documented layout, and the
+host-side argument checks return the documented codes."""
+import ctypes as C
+import os
+import re
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mppi.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:mppi_status|const char \*)\s*(mppi_\w+)\(", text, re.M)))
+
+
+def test_header_declares_the_api():
+    names = declared_functions()
+    for must in ("mppi_create", "mppi_destroy", "mppi_reserve", "mppi_update", "mppi_rollout",
+                 "mppi_weights", "mppi_weighted_sum", "mppi_apply_shift", "mppi_noise",
+                 "mppi_philox", "mppi_plant_step", "mppi_validate", "mppi_status_str",
+                 "mppi_last_error", "mppi_profile_enable", "mppi_profile_read"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2407_09812_amd as lib
+    so = C.CDLL(lib.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(so, name), name
+    assert set(lib.exported_symbols()) == set(declared_functions())
+    if shutil.which("nm"):
+        out = subprocess.run(["nm", "-D", "--defined-only", lib.LIB_PATH], capture_output=True,
+                             text=True, check=True).stdout
+        exported = set(re.findall(r"\bT (mppi_\w+)$", out, re.M))
+        assert set(declared_functions()) <= exported
+
+
+def test_struct_layouts():
+    import paper_2407_09812_amd as lib
+    assert C.sizeof(lib.Vehicle) == 13 * 4
+    assert C.sizeof(lib.Cost) == 15 * 4
+    assert C.sizeof(lib.Solve) == 64 and lib.Solve.seed.offset == 48
+    assert C.sizeof(lib.Diag) == 32
+    assert lib.OBSTACLE_DTYPE.itemsize == 20
+
+
+def _good():
+    sc = W.c2_line(K=128, N=10)
+    return sc.veh, sc.cost, sc.solve(0)
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("K", 0, -1), ("N", 0, -1), ("N", 4097, -1), ("dt", 0.0, -1), ("dt", -1.0, -1),
+    ("lam", 0.0, -1), ("lam", -2.0, -1), ("lam", float("nan"), -2), ("dt", float("inf"), -2),
+])
+def test_validate_solve_codes(field, value, code):
+    import paper_2407_09812_amd as lib
+    veh, cost, solve = _good()
+    assert lib.mppi_validate(veh, cost, solve, 20) == 0
+    solve[field] = value
+    assert lib.mppi_validate(veh, cost, solve, 20) == code
+
+
+def test_validate_other_codes():
+    import paper_2407_09812_amd as lib
+    veh, cost, solve = _good()
+    assert lib.mppi_validate(veh, cost, solve, -1) == -1
+    assert lib.mppi_validate(veh, cost, solve, lib.M_MAX + 1) == -1
+    s2 = dict(solve, sigma=np.array([1.0, -0.1, 1.0, 1.0]))
+    assert lib.mppi_validate(veh, cost, s2, 0) == -1
+    for k, v, code in (("mass", 0.0, -1), ("T_min", 9.0, -1), ("tau_m", -0.01, -1),
+                       ("g", float("nan"), -2)):
+        assert lib.mppi_validate(dict(veh, **{k: v}), cost, solve, 0) == code
+    assert lib.mppi_validate(veh, dict(cost, c_p=-1.0), solve, 0) == -1
+    assert lib.mppi_validate(veh, dict(cost, obs_w=float("inf")), solve, 0) == -2
+
+
+def test_null_context_is_rejected_without_device_access():
+    import paper_2407_09812_amd as lib
+    f = lib._lib
+    assert f.mppi_update(None, None, None, None, None, None, None, None, 0, None, None, None) == -1
+    assert f.mppi_reserve(None, 1, 1, 0) == -1
+    assert f.mppi_destroy(None) == -1
+    assert f.mppi_last_error(None) == b"null context"
+    assert lib.mppi_status_str(-8) == "MPPI_E_CAPACITY"
+    assert lib.mppi_status_str(0) == "MPPI_OK"
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+def test_plain_c_program_links_the_abi(tmp_path):
+    """The header is plain C and the library links into a C program."""
+    import paper_2407_09812_amd as lib
+    src = tmp_path / "probe.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include "mppi.h"
+int main(void) {
+    mppi_vehicle v = {1.0f, {0.01f, 0.01f, 0.02f}, 0.15f, 0.012f, 9.81f, 0.0f, 8.0f,
+                      0.03f, 0.0f, 0.0f, 0.0f};
+    mppi_cost c = {400, 40, 20, 20, {0.01f, 0.05f, 0.05f, 0.1f}, {0.05f, 0.1f, 0.1f, 0.3f},
+                   0.3f, 1000.0f, 1.0e4f};
+    mppi_solve s = {256, 20, 0.01f, 1.0f, {1, 1, 1, 1}, {9.81f, 0, 0, 0}, 0, 0, 0};
+    int ok = mppi_validate(&v, &c, &s, 0);
+    s.lambda = 0.0f;
+    int bad = mppi_validate(&v, &c, &s, 0);
+    printf("%d %d %s\n", ok, bad, mppi_status_str(bad));
+    return 0;
+}
+''')
+    exe = tmp_path / "probe"
+    libdir = os.path.dirname(lib.LIB_PATH)
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    "-o", str(exe), str(src), "-L", libdir, "-lmppi", f"-Wl,-rpath,{libdir}"],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    assert out == ["0", "-1", "MPPI_E_INVALID_ARG"]
