@@ -238,6 +238,23 @@ def run(args):
     return out
 
 
+def calibrate_copy(mib: int, reps: int):
+    """A plain device-to-device copy of known size, run under the same HBM counters as
+    the kernels so that FETCH_SIZE / WRITE_SIZE can be scaled to bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.rand(n, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    return {"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "reps": reps,
+            "GBps_read_plus_write": 8 * n / el / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,7 +263,12 @@ def main():
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="oracle CPU-baseline time budget (0 skips it)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy > 0:
+        print(json.dumps(calibrate_copy(args.calibrate_copy, 5)), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the MPPI update of one vehicle runs on one device; see the design notes "

@@ -11,7 +11,9 @@ namespace mppi {
 constexpr int kWeightsThreads = 1024;
 constexpr int kSumThreads = 256;
 
-// Arguments of the rollout kernel, passed by value in the kernel-argument segment.
+// Arguments of the rollout kernel.  The read-only inputs travel as separate
+// __restrict__ kernel arguments so that their wave-uniform rows are fetched with
+// scalar loads.
 struct RolloutArgs {
     ModelParams mp;
     CostParams cp;
@@ -26,6 +28,14 @@ struct RolloutArgs {
     int ld;
     float* S;                    // K
     float* states;               // [N+1][17][ld] or nullptr
+};
+
+// The scalar part of RolloutArgs, passed by value.
+struct RolloutParams {
+    ModelParams mp;
+    CostParams cp;
+    NoiseParams np;
+    int M, K, N, ld;
 };
 
 hipError_t launch_rollout(const RolloutArgs& a, int block, hipStream_t stream);

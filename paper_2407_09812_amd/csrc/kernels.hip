@@ -23,17 +23,20 @@ namespace mppi {
 // G1: rollouts and costs
 // ---------------------------------------------------------------------------
 
-template <bool kDump>
-__global__ __launch_bounds__(256) void rollout_kernel(RolloutArgs a)
+template <bool kLag, bool kDump>
+__global__ __launch_bounds__(256) void rollout_kernel(
+    RolloutParams a, const float* __restrict__ x_hat, const float* __restrict__ x_ref,
+    const mppi_obstacle* __restrict__ obs, const float* __restrict__ u_nom,
+    float* __restrict__ du_out, float* __restrict__ S_out, float* __restrict__ states)
 {
     extern __shared__ float4 obs_lds[];   // 2 x M float4
-    const float phx = a.x_hat[0], phy = a.x_hat[1], phz = a.x_hat[2];
+    const float phx = x_hat[0], phy = x_hat[1], phz = x_hat[2];
 
     // Stage the obstacle list once per workgroup, centred on x_hat's position:
     // the rollouts integrate positions relative to p_hat, which keeps binary32
     // rounding at the scale of the excursion rather than of the world frame.
     for (int i = threadIdx.x; i < a.M; i += blockDim.x) {
-        const mppi_obstacle o = a.obs[i];
+        const mppi_obstacle o = obs[i];
         const float R = o.r + a.cp.margin;
         obs_lds[2 * i] = make_float4(o.c[0] - phx, o.c[1] - phy, o.c[2] - phz,
                                      o.type == MPPI_VCYLINDER ? 0.0f : 1.0f);
@@ -47,32 +50,32 @@ __global__ __launch_bounds__(256) void rollout_kernel(RolloutArgs a)
 
     State x;
     x.px = 0.0f; x.py = 0.0f; x.pz = 0.0f;
-    x.qw = a.x_hat[3]; x.qx = a.x_hat[4]; x.qy = a.x_hat[5]; x.qz = a.x_hat[6];
-    x.vx = a.x_hat[7]; x.vy = a.x_hat[8]; x.vz = a.x_hat[9];
-    x.wx = a.x_hat[10]; x.wy = a.x_hat[11]; x.wz = a.x_hat[12];
-    x.T0 = a.x_hat[13]; x.T1 = a.x_hat[14]; x.T2 = a.x_hat[15]; x.T3 = a.x_hat[16];
+    x.qw = x_hat[3]; x.qx = x_hat[4]; x.qy = x_hat[5]; x.qz = x_hat[6];
+    x.vx = x_hat[7]; x.vy = x_hat[8]; x.vz = x_hat[9];
+    x.wx = x_hat[10]; x.wy = x_hat[11]; x.wz = x_hat[12];
+    x.T0 = x_hat[13]; x.T1 = x_hat[14]; x.T2 = x_hat[15]; x.T3 = x_hat[16];
 
     if (kDump) {   // trajectories [N+1][17][ld], positions back in the world frame
         const float vals[17] = {x.px + phx, x.py + phy, x.pz + phz, x.qw, x.qx, x.qy, x.qz,
                                 x.vx, x.vy, x.vz, x.wx, x.wy, x.wz, x.T0, x.T1, x.T2, x.T3};
 #pragma unroll
-        for (int i = 0; i < 17; ++i) a.states[(size_t)i * ld + k] = vals[i];
+        for (int i = 0; i < 17; ++i) states[(size_t)i * ld + k] = vals[i];
     }
 
     KahanSum S;
     // state j = 0 (the estimate itself) is scored like every other state (Eq. (17))
-    S.add(tracking_cost(a.cp, x, a.x_ref[0] - phx, a.x_ref[1] - phy, a.x_ref[2] - phz, a.x_ref) +
+    S.add(tracking_cost(a.cp, x, x_ref[0] - phx, x_ref[1] - phy, x_ref[2] - phz, x_ref) +
           obstacle_cost(a.cp, x.px, x.py, x.pz, obs_lds, a.M));
 
     float up[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int j = 0; j < a.N; ++j) {
         float du[4], u[4];
         draw_noise(a.np, (uint32_t)k, (uint32_t)j, du);
-        float* dst = a.du + (size_t)(4 * j) * ld + k;
+        float* dst = du_out + (size_t)(4 * j) * ld + k;
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
             dst[(size_t)d * ld] = du[d];
-            u[d] = a.u_nom[4 * j + d] + du[d];          // Eq. (2): u = u_nom + delta_u
+            u[d] = u_nom[4 * j + d] + du[d];            // Eq. (2): u = u_nom + delta_u
         }
         // input and input-change terms of Eq. (16)
         float cu = 0.0f;
@@ -90,9 +93,9 @@ __global__ __launch_bounds__(256) void rollout_kernel(RolloutArgs a)
 
         float Tc[4];
         rate_controller(a.mp, x.wx, x.wy, x.wz, u, Tc);
-        rk4_step(a.mp, x, Tc);
+        rk4_step<kLag>(a.mp, x, Tc);
 
-        const float* ref = a.x_ref + (size_t)13 * (j + 1);
+        const float* ref = x_ref + (size_t)13 * (j + 1);
         const float cx = tracking_cost(a.cp, x, ref[0] - phx, ref[1] - phy, ref[2] - phz, ref) +
                          obstacle_cost(a.cp, x.px, x.py, x.pz, obs_lds, a.M);
         S.add(cu + cx);
@@ -100,12 +103,12 @@ __global__ __launch_bounds__(256) void rollout_kernel(RolloutArgs a)
         if (kDump) {
             const float vals[17] = {x.px + phx, x.py + phy, x.pz + phz, x.qw, x.qx, x.qy, x.qz,
                                     x.vx, x.vy, x.vz, x.wx, x.wy, x.wz, x.T0, x.T1, x.T2, x.T3};
-            float* st = a.states + (size_t)17 * (j + 1) * ld + k;
+            float* st = states + (size_t)17 * (j + 1) * ld + k;
 #pragma unroll
             for (int i = 0; i < 17; ++i) st[(size_t)i * ld] = vals[i];
         }
     }
-    a.S[k] = S.s;
+    S_out[k] = S.s;
 }
 
 // ---------------------------------------------------------------------------
@@ -310,7 +313,10 @@ __global__ void plant_kernel(ModelParams P, const float* __restrict__ x_in,
     const float u[4] = {u_in[0], u_in[1], u_in[2], u_in[3]};
     float Tc[4];
     rate_controller(P, x.wx, x.wy, x.wz, u, Tc);
-    rk4_step(P, x, Tc);
+    if (P.lag)
+        rk4_step<true>(P, x, Tc);
+    else
+        rk4_step<false>(P, x, Tc);
     const float out[17] = {x.px, x.py, x.pz, x.qw, x.qx, x.qy, x.qz, x.vx, x.vy, x.vz,
                            x.wx, x.wy, x.wz, x.T0, x.T1, x.T2, x.T3};
     for (int i = 0; i < 17; ++i) x_out[i] = out[i];
@@ -343,10 +349,11 @@ hipError_t launch_rollout(const RolloutArgs& a, int block, hipStream_t stream)
 {
     const int grid = (a.K + block - 1) / block;
     const size_t lds = sizeof(float4) * 2 * (size_t)a.M;
-    if (a.states)
-        hipLaunchKernelGGL(rollout_kernel<true>, dim3(grid), dim3(block), lds, stream, a);
-    else
-        hipLaunchKernelGGL(rollout_kernel<false>, dim3(grid), dim3(block), lds, stream, a);
+    const RolloutParams p{a.mp, a.cp, a.np, a.M, a.K, a.N, a.ld};
+    auto kernel = a.mp.lag ? (a.states ? rollout_kernel<true, true> : rollout_kernel<true, false>)
+                           : (a.states ? rollout_kernel<false, true> : rollout_kernel<false, false>);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), lds, stream, p, a.x_hat, a.x_ref, a.obs,
+                       a.u_nom, a.du, a.S, a.states);
     return hipGetLastError();
 }
 

@@ -63,9 +63,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;   // one v_mad_u64_u32 each
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+                       (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -126,11 +127,12 @@ __device__ __forceinline__ void rate_controller(const ModelParams& P, float wx, 
 // Dynamics (Eq. (6)) and RK4 (Eq. (2))
 // ---------------------------------------------------------------------------
 
+template <bool kLag>
 __device__ __forceinline__ void derivative(const ModelParams& P, const State& x, const float Tc[4],
                                            State& d)
 {
-    const float T0 = P.lag ? x.T0 : Tc[0], T1 = P.lag ? x.T1 : Tc[1];
-    const float T2 = P.lag ? x.T2 : Tc[2], T3 = P.lag ? x.T3 : Tc[3];
+    const float T0 = kLag ? x.T0 : Tc[0], T1 = kLag ? x.T1 : Tc[1];
+    const float T2 = kLag ? x.T2 : Tc[2], T3 = kLag ? x.T3 : Tc[3];
     // Eq. (13): [F; tau] = Gamma T
     const float s01 = T0 + T1, s23 = T2 + T3, d10 = T1 - T0, d23 = T2 - T3;
     const float F = s01 + s23;
@@ -153,10 +155,14 @@ __device__ __forceinline__ void derivative(const ModelParams& P, const State& x,
     d.wy = (ty - P.G[1] * (x.wz * x.wx)) * P.J_inv[1];
     d.wz = (tz - P.G[2] * (x.wx * x.wy)) * P.J_inv[2];
     // rotor lag T' = (T_cmd - T) / tau_m
-    d.T0 = (Tc[0] - x.T0) * P.tau_inv;
-    d.T1 = (Tc[1] - x.T1) * P.tau_inv;
-    d.T2 = (Tc[2] - x.T2) * P.tau_inv;
-    d.T3 = (Tc[3] - x.T3) * P.tau_inv;
+    if (kLag) {
+        d.T0 = (Tc[0] - x.T0) * P.tau_inv;
+        d.T1 = (Tc[1] - x.T1) * P.tau_inv;
+        d.T2 = (Tc[2] - x.T2) * P.tau_inv;
+        d.T3 = (Tc[3] - x.T3) * P.tau_inv;
+    } else {
+        d.T0 = d.T1 = d.T2 = d.T3 = 0.0f;
+    }
 }
 
 #define MPPI_STATE_FIELDS(X) \
@@ -164,30 +170,31 @@ __device__ __forceinline__ void derivative(const ModelParams& P, const State& x,
     X(T0) X(T1) X(T2) X(T3)
 
 // One step x <- x + f_RK4(x, Tc, dt) with the command held, then q <- q / |q|.
+template <bool kLag>
 __device__ __forceinline__ void rk4_step(const ModelParams& P, State& x, const float Tc[4])
 {
     const float h = P.dt, h2 = 0.5f * P.dt, h6 = P.dt * (1.0f / 6.0f);
     State k, xs, acc;
-    derivative(P, x, Tc, k);                                     // k1
+    derivative<kLag>(P, x, Tc, k);                               // k1
 #define STAGE1(f) acc.f = k.f; xs.f = fmaf(h2, k.f, x.f);
     MPPI_STATE_FIELDS(STAGE1)
 #undef STAGE1
-    derivative(P, xs, Tc, k);                                    // k2
+    derivative<kLag>(P, xs, Tc, k);                              // k2
 #define STAGE2(f) acc.f = fmaf(2.0f, k.f, acc.f); xs.f = fmaf(h2, k.f, x.f);
     MPPI_STATE_FIELDS(STAGE2)
 #undef STAGE2
-    derivative(P, xs, Tc, k);                                    // k3
+    derivative<kLag>(P, xs, Tc, k);                              // k3
 #define STAGE3(f) acc.f = fmaf(2.0f, k.f, acc.f); xs.f = fmaf(h, k.f, x.f);
     MPPI_STATE_FIELDS(STAGE3)
 #undef STAGE3
-    derivative(P, xs, Tc, k);                                    // k4
+    derivative<kLag>(P, xs, Tc, k);                              // k4
 #define STAGE4(f) x.f = fmaf(h6, acc.f + k.f, x.f);
     MPPI_STATE_FIELDS(STAGE4)
 #undef STAGE4
     const float n2 = x.qw * x.qw + x.qx * x.qx + x.qy * x.qy + x.qz * x.qz;
     const float inv = __builtin_amdgcn_rsqf(n2);
     x.qw *= inv; x.qx *= inv; x.qy *= inv; x.qz *= inv;
-    if (!P.lag) { x.T0 = Tc[0]; x.T1 = Tc[1]; x.T2 = Tc[2]; x.T3 = Tc[3]; }
+    if (!kLag) { x.T0 = Tc[0]; x.T1 = Tc[1]; x.T2 = Tc[2]; x.T3 = Tc[3]; }
 }
 
 // ---------------------------------------------------------------------------
