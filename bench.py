@@ -255,6 +255,20 @@ def calibrate_copy(mib: int, reps: int):
             "GBps_read_plus_write": 8 * n / el / 1e9}
 
 
+def summarize_rocpd(db_path: str, command: str) -> str:
+    """Markdown table of per-kernel calls / total / average duration from a rocprofv3
+    rocpd database (kernel trace)."""
+    import sqlite3
+    db = sqlite3.connect(db_path)
+    rows = db.execute("select name, total_calls, total_duration, average, percentage "
+                      "from top_kernels").fetchall()
+    out = [f"Command:\n\n    {command}\n", "| kernel | calls | total (us) | average (us) | % |",
+           "|---|---:|---:|---:|---:|"]
+    for name, calls, total, avg, pct in rows:
+        out.append(f"| `{name.split('(')[0]}` | {calls} | {total:.1f} | {avg:.3f} | {pct:.1f} |")
+    return "\n".join(out) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,7 +279,12 @@ def main():
                     help="oracle CPU-baseline time budget (0 skips it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--summarize-rocpd", nargs=2, metavar=("DB", "COMMAND"),
+                    help="print a Markdown kernel summary of a rocprofv3 database and exit")
     args = ap.parse_args()
+    if args.summarize_rocpd:
+        sys.stdout.write(summarize_rocpd(*args.summarize_rocpd))
+        return
     if args.calibrate_copy > 0:
         print(json.dumps(calibrate_copy(args.calibrate_copy, 5)), flush=True)
         return
