@@ -152,6 +152,12 @@ def run(args):
     lib.mppi_reserve(ctx, K, N, M)
     stream = torch.cuda.current_stream()
     solves = [sc.solve(t) for t in range(total)]
+    if args.autotune:
+        launch = lib.mppi_autotune(ctx, sc.veh, sc.cost, solves[0], x_buf[0], refs[0], obs, M, u_nom,
+                                   reps=3, stream=stream)
+    else:
+        launch = lib.mppi_get_config(ctx, K, N, M)
+    log(f"bench: rollout launch shape {launch}")
 
     lat = []
 
@@ -210,7 +216,7 @@ def run(args):
         "data": "synthetic",
         "config": {"workload": f"{sc.name}: single vehicle, K={K}, N={N}, dt={sc.dt}, M={M}, "
                                f"closed loop (plain: one solve per launch sequence)",
-                   "K": K, "N": N, "M": M, "updates": steps},
+                   "K": K, "N": N, "M": M, "updates": steps, "rollout_launch": launch},
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99),
                        "mean": sum(lat) / len(lat)},
         "device_ms_per_update": {"rollout": rollout_ms, "weights": prof["weights_ms"] / n_upd,
@@ -275,6 +281,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="use the library's default rollout launch shape")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="oracle CPU-baseline time budget (0 skips it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",

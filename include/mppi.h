@@ -202,6 +202,36 @@ mppi_status mppi_philox(mppi_ctx *ctx, void *stream, int32_t n, const uint32_t *
 mppi_status mppi_plant_step(mppi_ctx *ctx, void *stream, const mppi_vehicle *veh, float dt,
                             const float *x, const float *u, float *x_out);
 
+/* --- launch shape and autotuning ----------------------------------------------- */
+
+/* Shape of the rollout launch: `lanes` consecutive lanes share one sample and divide
+ * its obstacle tests (1, 2, 4, 8); `block` threads per workgroup (64, 128, 256);
+ * obstacle loop unrolled `unroll` times (1, 4).  Every shape computes the same update;
+ * only the order of the obstacle-penalty additions (hence rounding) depends on lanes. */
+typedef struct mppi_launch_config {
+    int32_t block;
+    int32_t lanes;
+    int32_t unroll;
+} mppi_launch_config;
+
+/* The shape mppi_update / mppi_rollout use for (K, N, M): a stored entry for the
+ * size class (powers of two of K, N and M), else a heuristic that aims at one wave
+ * per SIMD.  Host-only. */
+mppi_status mppi_get_config(const mppi_ctx *ctx, int32_t K, int32_t N, int32_t M,
+                            mppi_launch_config *out);
+/* Store a shape for the size class of (K, N, M).  MPPI_E_INVALID_ARG for a shape
+ * outside the lists above.  Host-only. */
+mppi_status mppi_set_config(mppi_ctx *ctx, int32_t K, int32_t N, int32_t M,
+                            const mppi_launch_config *cfg);
+/* Time every shape on these inputs (reps launches each, HIP events on `stream`),
+ * store the fastest for the size class and return it in best.  Uses the context's
+ * scratch (mppi_reserve first) and synchronises the stream; a set-up call, not for
+ * the update loop. */
+mppi_status mppi_autotune(mppi_ctx *ctx, void *stream, const mppi_vehicle *veh,
+                          const mppi_cost *cost, const mppi_solve *solve, const float *x_hat,
+                          const float *x_ref, const mppi_obstacle *obs, int32_t M,
+                          const float *u_nom, int32_t reps, mppi_launch_config *best);
+
 /* --- profiling ---------------------------------------------------------------- */
 
 /* Per-kernel device time of mppi_update, measured with HIP events on the

@@ -64,6 +64,10 @@ class Diag(C.Structure):
                 ("reserved", C.c_float * 2)]
 
 
+class LaunchConfig(C.Structure):
+    _fields_ = [("block", C.c_int32), ("lanes", C.c_int32), ("unroll", C.c_int32)]
+
+
 class Profile(C.Structure):
     _fields_ = [("updates", C.c_int64), ("rollout_ms", C.c_double), ("weights_ms", C.c_double),
                 ("reduce_ms", C.c_double), ("apply_ms", C.c_double)]
@@ -94,6 +98,10 @@ _SIGS = {
     "mppi_noise": [_vp, _vp, _PS, _vp, _i32],
     "mppi_philox": [_vp, _vp, _i32, _vp, _vp, _vp],
     "mppi_plant_step": [_vp, _vp, _PV, _f32, _vp, _vp, _vp],
+    "mppi_get_config": [_vp, _i32, _i32, _i32, C.POINTER(LaunchConfig)],
+    "mppi_set_config": [_vp, _i32, _i32, _i32, C.POINTER(LaunchConfig)],
+    "mppi_autotune": [_vp, _vp, _PV, _PC, _PS, _vp, _vp, _vp, _i32, _vp, _i32,
+                      C.POINTER(LaunchConfig)],
     "mppi_profile_enable": [_vp, _i32],
     "mppi_profile_read": [_vp, C.POINTER(Profile)],
 }
@@ -278,6 +286,26 @@ def mppi_plant_step(ctx, veh, dt, x, u, x_out, stream=None):
     v = vehicle(veh)
     ctx.check(_lib.mppi_plant_step(ctx.handle, _stream(stream), C.byref(v), float(dt), _ptr(x),
                                    _ptr(u), _ptr(x_out)), "mppi_plant_step")
+
+
+def mppi_get_config(ctx, K, N, M) -> dict:
+    c = LaunchConfig()
+    ctx.check(_lib.mppi_get_config(ctx.handle, int(K), int(N), int(M), C.byref(c)), "mppi_get_config")
+    return dict(block=c.block, lanes=c.lanes, unroll=c.unroll)
+
+
+def mppi_set_config(ctx, K, N, M, block, lanes, unroll):
+    c = LaunchConfig(int(block), int(lanes), int(unroll))
+    ctx.check(_lib.mppi_set_config(ctx.handle, int(K), int(N), int(M), C.byref(c)), "mppi_set_config")
+
+
+def mppi_autotune(ctx, veh, cst, slv, x_hat, x_ref, obs_dev, M, u_nom, reps=3, stream=None) -> dict:
+    v, c, s = vehicle(veh), cost(cst), solve(slv)
+    best = LaunchConfig()
+    ctx.check(_lib.mppi_autotune(ctx.handle, _stream(stream), C.byref(v), C.byref(c), C.byref(s),
+                                 _ptr(x_hat), _ptr(x_ref), _ptr(obs_dev) if M > 0 else None,
+                                 int(M), _ptr(u_nom), int(reps), C.byref(best)), "mppi_autotune")
+    return dict(block=best.block, lanes=best.lanes, unroll=best.unroll)
 
 
 def mppi_profile_enable(ctx, on=True):

@@ -5,8 +5,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "kernels.h"
@@ -21,7 +23,7 @@ struct mppi_ctx {
     float* w = nullptr;         // [ld]
     float* u_upd = nullptr;     // [N_cap][4]
     mppi_diag* diag = nullptr;  // 1
-    int rollout_block = 64;
+    std::map<std::tuple<int, int, int>, LaunchConfig> tuned;   // size class -> shape
     std::string last_error;
     // profiling: 5 events per update bracket rollout, weights, sum, apply
     bool profiling = false;
@@ -162,6 +164,38 @@ void free_scratch(mppi_ctx* ctx)
     ctx->K_cap = ctx->N_cap = ctx->M_cap = ctx->ld = 0;
 }
 
+int ceil_log2(int v)
+{
+    int b = 0;
+    while ((1 << b) < v) ++b;
+    return b;
+}
+
+std::tuple<int, int, int> size_class(int K, int N, int M)
+{
+    return {ceil_log2(K), ceil_log2(N), M == 0 ? -1 : ceil_log2(M)};
+}
+
+// One wave per SIMD (1024 on the chip) is the target for a lone instance; lanes
+// beyond one per sample only pay off when there are obstacles to divide.
+LaunchConfig heuristic_config(int K, int M)
+{
+    const int waves = (K + 63) / 64;
+    int lanes = 1;
+    while (lanes < 8 && waves * lanes * 2 <= 1024 && M >= 8 * lanes) lanes *= 2;
+    LaunchConfig c;
+    c.lanes = lanes;
+    c.block = (waves * lanes >= 1024) ? 256 : 64;
+    c.unroll = M >= 16 ? 4 : 1;
+    return c;
+}
+
+LaunchConfig config_for(const mppi_ctx* ctx, int K, int N, int M)
+{
+    auto it = ctx->tuned.find(size_class(K, N, M));
+    return it != ctx->tuned.end() ? it->second : heuristic_config(K, M);
+}
+
 hipEvent_t take_event(mppi_ctx* ctx)
 {
     if (!ctx->pool.empty()) {
@@ -296,7 +330,7 @@ mppi_status mppi_update(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh, co
     };
 
     HIP_TRY(ctx, mark(0));
-    HIP_TRY(ctx, launch_rollout(a, ctx->rollout_block, s));
+    HIP_TRY(ctx, launch_rollout(a, config_for(ctx, solve->K, solve->N, M), s));
     HIP_TRY(ctx, mark(1));
     HIP_TRY(ctx, launch_weights(ctx->S, solve->K, solve->lambda, ctx->w, dg, s));
     HIP_TRY(ctx, mark(2));
@@ -324,7 +358,73 @@ mppi_status mppi_rollout(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh, c
     RolloutArgs a = rollout_args(*veh, *cost, *solve);
     a.x_hat = x_hat; a.x_ref = x_ref; a.obs = obs; a.M = M; a.u_nom = u_nom;
     a.du = du; a.ld = ld; a.S = S; a.states = states;
-    HIP_TRY(ctx, launch_rollout(a, ctx->rollout_block, (hipStream_t)stream));
+    HIP_TRY(ctx, launch_rollout(a, config_for(ctx, solve->K, solve->N, M), (hipStream_t)stream));
+    return MPPI_OK;
+}
+
+mppi_status mppi_get_config(const mppi_ctx* ctx, int32_t K, int32_t N, int32_t M,
+                            mppi_launch_config* out)
+{
+    if (!ctx || !out || K < 1 || N < 1 || M < 0) return MPPI_E_INVALID_ARG;
+    const LaunchConfig c = config_for(ctx, K, N, M);
+    out->block = c.block; out->lanes = c.lanes; out->unroll = c.unroll;
+    return MPPI_OK;
+}
+
+mppi_status mppi_set_config(mppi_ctx* ctx, int32_t K, int32_t N, int32_t M,
+                            const mppi_launch_config* cfg)
+{
+    if (!ctx || !cfg || K < 1 || N < 1 || M < 0) return MPPI_E_INVALID_ARG;
+    const LaunchConfig c{cfg->block, cfg->lanes, cfg->unroll};
+    if (!valid_config(c)) return fail(ctx, MPPI_E_INVALID_ARG, "set_config: invalid shape");
+    ctx->tuned[size_class(K, N, M)] = c;
+    return MPPI_OK;
+}
+
+mppi_status mppi_autotune(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh, const mppi_cost* cost,
+                          const mppi_solve* solve, const float* x_hat, const float* x_ref,
+                          const mppi_obstacle* obs, int32_t M, const float* u_nom, int32_t reps,
+                          mppi_launch_config* best)
+{
+    if (!ctx) return MPPI_E_INVALID_ARG;
+    mppi_status st = mppi_validate(veh, cost, solve, M);
+    if (st != MPPI_OK) return fail(ctx, st, "autotune: invalid parameters");
+    if (!x_hat || !x_ref || !u_nom || (M > 0 && !obs) || reps < 1)
+        return fail(ctx, MPPI_E_INVALID_ARG, "autotune: bad argument");
+    if (solve->K > ctx->K_cap || solve->N > ctx->N_cap)
+        return fail(ctx, MPPI_E_CAPACITY, "autotune: request exceeds reserved scratch");
+    hipStream_t s = (hipStream_t)stream;
+    RolloutArgs a = rollout_args(*veh, *cost, *solve);
+    a.x_hat = x_hat; a.x_ref = x_ref; a.obs = obs; a.M = M; a.u_nom = u_nom;
+    a.du = ctx->du; a.ld = ctx->ld; a.S = ctx->S; a.states = nullptr;
+    hipEvent_t e0 = take_event(ctx), e1 = take_event(ctx);
+    if (!e0 || !e1) return fail(ctx, MPPI_E_HIP, "autotune: event creation");
+    LaunchConfig best_c{};
+    float best_ms = 1e30f;
+    mppi_status result = MPPI_OK;
+    for (int lanes : {1, 2, 4, 8}) {
+        if (lanes > 1 && M < 2 * lanes) continue;        // nothing to divide
+        for (int block : {64, 128, 256})
+            for (int unroll : {1, 4}) {
+                if (unroll > 1 && M < 8) continue;
+                const LaunchConfig c{block, lanes, unroll};
+                hipError_t e = launch_rollout(a, c, s);   // warm-up
+                if (e == hipSuccess) e = hipEventRecord(e0, s);
+                for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_rollout(a, c, s);
+                if (e == hipSuccess) e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) { result = hip_fail(ctx, e, "autotune"); break; }
+                if (ms < best_ms) { best_ms = ms; best_c = c; }
+            }
+        if (result != MPPI_OK) break;
+    }
+    ctx->pool.push_back(e0);
+    ctx->pool.push_back(e1);
+    if (result != MPPI_OK) return result;
+    ctx->tuned[size_class(solve->K, solve->N, M)] = best_c;
+    if (best) { best->block = best_c.block; best->lanes = best_c.lanes; best->unroll = best_c.unroll; }
     return MPPI_OK;
 }
 

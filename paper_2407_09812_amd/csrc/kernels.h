@@ -38,7 +38,16 @@ struct RolloutParams {
     int M, K, N, ld;
 };
 
-hipError_t launch_rollout(const RolloutArgs& a, int block, hipStream_t stream);
+// Rollout launch shape: `lanes` consecutive lanes per sample (the obstacle tests are
+// divided among them), `block` threads per workgroup, obstacle loop unrolled `unroll`.
+struct LaunchConfig {
+    int block;    // 64, 128, 256
+    int lanes;    // 1, 2, 4, 8
+    int unroll;   // 1, 4
+};
+
+bool valid_config(const LaunchConfig& c);
+hipError_t launch_rollout(const RolloutArgs& a, const LaunchConfig& cfg, hipStream_t stream);
 hipError_t launch_weights(const float* S, int K, float lambda, float* w, mppi_diag* diag,
                           hipStream_t stream);
 hipError_t launch_weighted_sum(const float* w, const float* du, int K, int N, int ld,

@@ -23,7 +23,7 @@ namespace mppi {
 // G1: rollouts and costs
 // ---------------------------------------------------------------------------
 
-template <bool kLag, bool kDump>
+template <int L, int U, bool kLag, bool kDump>
 __global__ __launch_bounds__(256) void rollout_kernel(
     RolloutParams a, const float* __restrict__ x_hat, const float* __restrict__ x_ref,
     const mppi_obstacle* __restrict__ obs, const float* __restrict__ u_nom,
@@ -44,8 +44,12 @@ __global__ __launch_bounds__(256) void rollout_kernel(
     }
     __syncthreads();
 
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    // L consecutive lanes integrate the same sample (identical instructions and
+    // operands, hence identical trajectories); lane q = 0 of the group writes.
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = g / L, q = g % L;
     if (k >= a.K) return;
+    const bool writer = (q == 0);
     const size_t ld = (size_t)a.ld;
 
     State x;
@@ -55,7 +59,7 @@ __global__ __launch_bounds__(256) void rollout_kernel(
     x.wx = x_hat[10]; x.wy = x_hat[11]; x.wz = x_hat[12];
     x.T0 = x_hat[13]; x.T1 = x_hat[14]; x.T2 = x_hat[15]; x.T3 = x_hat[16];
 
-    if (kDump) {   // trajectories [N+1][17][ld], positions back in the world frame
+    if (kDump && writer) {   // trajectories [N+1][17][ld], positions back in the world frame
         const float vals[17] = {x.px + phx, x.py + phy, x.pz + phz, x.qw, x.qx, x.qy, x.qz,
                                 x.vx, x.vy, x.vz, x.wx, x.wy, x.wz, x.T0, x.T1, x.T2, x.T3};
 #pragma unroll
@@ -65,18 +69,19 @@ __global__ __launch_bounds__(256) void rollout_kernel(
     KahanSum S;
     // state j = 0 (the estimate itself) is scored like every other state (Eq. (17))
     S.add(tracking_cost(a.cp, x, x_ref[0] - phx, x_ref[1] - phy, x_ref[2] - phz, x_ref) +
-          obstacle_cost(a.cp, x.px, x.py, x.pz, obs_lds, a.M));
+          obstacle_cost<L, U>(a.cp, x.px, x.py, x.pz, obs_lds, a.M, q));
 
     float up[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int j = 0; j < a.N; ++j) {
         float du[4], u[4];
         draw_noise(a.np, (uint32_t)k, (uint32_t)j, du);
-        float* dst = du_out + (size_t)(4 * j) * ld + k;
+        if (writer) {
+            float* dst = du_out + (size_t)(4 * j) * ld + k;
 #pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            dst[(size_t)d * ld] = du[d];
-            u[d] = u_nom[4 * j + d] + du[d];            // Eq. (2): u = u_nom + delta_u
+            for (int d = 0; d < 4; ++d) dst[(size_t)d * ld] = du[d];
         }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) u[d] = u_nom[4 * j + d] + du[d];   // Eq. (2): u = u_nom + du
         // input and input-change terms of Eq. (16)
         float cu = 0.0f;
 #pragma unroll
@@ -97,10 +102,10 @@ __global__ __launch_bounds__(256) void rollout_kernel(
 
         const float* ref = x_ref + (size_t)13 * (j + 1);
         const float cx = tracking_cost(a.cp, x, ref[0] - phx, ref[1] - phy, ref[2] - phz, ref) +
-                         obstacle_cost(a.cp, x.px, x.py, x.pz, obs_lds, a.M);
+                         obstacle_cost<L, U>(a.cp, x.px, x.py, x.pz, obs_lds, a.M, q);
         S.add(cu + cx);
 
-        if (kDump) {
+        if (kDump && writer) {
             const float vals[17] = {x.px + phx, x.py + phy, x.pz + phz, x.qw, x.qx, x.qy, x.qz,
                                     x.vx, x.vy, x.vz, x.wx, x.wy, x.wz, x.T0, x.T1, x.T2, x.T3};
             float* st = states + (size_t)17 * (j + 1) * ld + k;
@@ -108,7 +113,7 @@ __global__ __launch_bounds__(256) void rollout_kernel(
             for (int i = 0; i < 17; ++i) st[(size_t)i * ld] = vals[i];
         }
     }
-    S_out[k] = S.s;
+    if (writer) S_out[k] = S.s;
 }
 
 // ---------------------------------------------------------------------------
@@ -345,16 +350,43 @@ __global__ void philox_kernel(int n, const uint4* __restrict__ ctr, const uint2*
 // Host-side launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_rollout(const RolloutArgs& a, int block, hipStream_t stream)
+bool valid_config(const LaunchConfig& c)
 {
-    const int grid = (a.K + block - 1) / block;
+    return (c.block == 64 || c.block == 128 || c.block == 256) &&
+           (c.lanes == 1 || c.lanes == 2 || c.lanes == 4 || c.lanes == 8) &&
+           (c.unroll == 1 || c.unroll == 4);
+}
+
+template <int L, int U>
+static hipError_t launch_rollout_lu(const RolloutArgs& a, int block, hipStream_t stream)
+{
+    const size_t threads = (size_t)a.K * L;
+    const int grid = (int)((threads + block - 1) / block);
     const size_t lds = sizeof(float4) * 2 * (size_t)a.M;
     const RolloutParams p{a.mp, a.cp, a.np, a.M, a.K, a.N, a.ld};
-    auto kernel = a.mp.lag ? (a.states ? rollout_kernel<true, true> : rollout_kernel<true, false>)
-                           : (a.states ? rollout_kernel<false, true> : rollout_kernel<false, false>);
+    auto kernel = a.mp.lag ? (a.states ? rollout_kernel<L, U, true, true> : rollout_kernel<L, U, true, false>)
+                           : (a.states ? rollout_kernel<L, U, false, true> : rollout_kernel<L, U, false, false>);
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), lds, stream, p, a.x_hat, a.x_ref, a.obs,
                        a.u_nom, a.du, a.S, a.states);
     return hipGetLastError();
+}
+
+template <int L>
+static hipError_t launch_rollout_l(const RolloutArgs& a, const LaunchConfig& c, hipStream_t stream)
+{
+    return c.unroll == 4 ? launch_rollout_lu<L, 4>(a, c.block, stream)
+                         : launch_rollout_lu<L, 1>(a, c.block, stream);
+}
+
+hipError_t launch_rollout(const RolloutArgs& a, const LaunchConfig& c, hipStream_t stream)
+{
+    if (!valid_config(c)) return hipErrorInvalidValue;
+    switch (c.lanes) {
+    case 1: return launch_rollout_l<1>(a, c, stream);
+    case 2: return launch_rollout_l<2>(a, c, stream);
+    case 4: return launch_rollout_l<4>(a, c, stream);
+    default: return launch_rollout_l<8>(a, c, stream);
+    }
 }
 
 hipError_t launch_weights(const float* S, int K, float lambda, float* w, mppi_diag* diag,

@@ -218,26 +218,54 @@ __device__ __forceinline__ float tracking_cost(const CostParams& C, const State&
     return c;
 }
 
+// Sum / OR over the L consecutive lanes that share one sample.  xor partners 1 and 2
+// use DPP quad permutations; 4 uses a cross-lane shuffle.  Every lane of the group
+// ends with the same value (the additions pair the same operands in every lane).
+__device__ __forceinline__ float dpp_xor1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float dpp_xor2(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+}
+
+template <int L>
+__device__ __forceinline__ float group_sum(float v)
+{
+    if (L >= 2) v += dpp_xor1(v);
+    if (L >= 4) v += dpp_xor2(v);
+    if (L >= 8) v += __shfl_xor(v, 4);
+    return v;
+}
+
 // Obstacles staged in LDS as two float4 per obstacle:
 //   a = (cx, cy, cz, zmask)  centre relative to the frame origin; zmask 0 for a
 //                            vertical cylinder (ignore z), 1 for a sphere
 //   b = (r^2, (r + margin)^2, r + margin, 0)
+// Lane q of a sample's L lanes tests obstacles q, q + L, q + 2L, ...; the partial
+// penalties and hit flags are then combined over the group.
+template <int L, int U>
 __device__ __forceinline__ float obstacle_cost(const CostParams& C, float px, float py, float pz,
-                                               const float4* __restrict__ obs, int M)
+                                               const float4* __restrict__ obs, int M, int q)
 {
-    bool hit = false;
-    float pen = 0.0f;
-    for (int i = 0; i < M; ++i) {
+    float hit = 0.0f, pen = 0.0f;
+#pragma unroll U
+    for (int i = q; i < M; i += L) {
         const float4 a = obs[2 * i], b = obs[2 * i + 1];
         const float dx = px - a.x, dy = py - a.y, dz = (pz - a.z) * a.w;
         const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        hit |= (d2 < b.x);
+        hit = d2 < b.x ? 1.0f : hit;
         if (d2 < b.y) {
             const float gap = b.z - __builtin_amdgcn_sqrtf(d2);
             pen = fmaf(gap, gap, pen);
         }
     }
-    return fmaf(C.w_obs, pen, hit ? C.c_col : 0.0f);
+    if (L > 1) {
+        pen = group_sum<L>(pen);
+        hit = group_sum<L>(hit);
+    }
+    return fmaf(C.w_obs, pen, hit > 0.0f ? C.c_col : 0.0f);
 }
 
 // Kahan-compensated accumulation of the rollout cost.

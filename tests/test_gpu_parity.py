@@ -157,6 +157,33 @@ def test_rollout_parity_paper_model(lib, ctx, orc):
     check_rollouts(orc, P, du, S, st, np.arange(P.K))
 
 
+@pytest.mark.parametrize("lanes,block,unroll", [(1, 64, 1), (2, 128, 4), (4, 64, 4), (8, 256, 1),
+                                                (8, 64, 4)])
+def test_rollout_parity_every_launch_shape(lib, ctx, orc, lanes, block, unroll):
+    """Each shape (lanes per sample dividing the obstacle tests, workgroup size,
+    unroll) computes the same rollouts; K = 700 leaves a partial last workgroup."""
+    P = DeviceProblem(lib, W.c2_line(K=700, N=60))
+    lib.mppi_set_config(ctx, P.K, P.N, P.M, block, lanes, unroll)
+    assert lib.mppi_get_config(ctx, P.K, P.N, P.M) == dict(block=block, lanes=lanes, unroll=unroll)
+    du, S, st = run_rollout(lib, ctx, P)
+    check_rollouts(orc, P, du, S, st, np.arange(P.K))
+    P3 = DeviceProblem(lib, W.c3_agile(K=2000, N=120))
+    lib.mppi_set_config(ctx, P3.K, P3.N, P3.M, block, lanes, unroll)
+    du, S, st = run_rollout(lib, ctx, P3)
+    check_rollouts(orc, P3, du, S, st, np.arange(0, P3.K, 13))
+
+
+def test_autotune_picks_a_valid_shape(lib, ctx, orc):
+    P = DeviceProblem(lib, W.c3_agile(K=4096, N=50))
+    best = lib.mppi_autotune(ctx, P.sc.veh, P.sc.cost, P.solve, P.x_hat, P.x_ref, P.obs, P.M,
+                             P.u_nom, reps=2)
+    print("autotuned", best)
+    assert best["lanes"] in (1, 2, 4, 8) and best["block"] in (64, 128, 256)
+    assert lib.mppi_get_config(ctx, P.K, P.N, P.M) == best
+    du, S, st = run_rollout(lib, ctx, P)
+    check_rollouts(orc, P, du, S, st, np.arange(0, P.K, 41))
+
+
 def test_rollout_edge_shapes(lib, ctx, orc):
     """K = 1, K = 65 (one lane in the last workgroup), N = 1, M = 0."""
     for K, N in ((1, 30), (65, 1), (130, 7)):
