@@ -275,12 +275,119 @@ def summarize_rocpd(db_path: str, command: str) -> str:
     return "\n".join(out) + "\n"
 
 
+def run_batched(args, steps: int, warmup: int, plain_steps: int):
+    """The batched configuration: 256 vehicles with uneven K, N and obstacle counts, one
+    batched update (persistent kernel, HIP graph) per step, against the same updates
+    issued as 256 sequential one-instance launch sequences."""
+    import numpy as np
+    import torch
+
+    import paper_2407_09812_amd as lib
+    import workloads as W
+
+    fleet = W.c4_batch()
+    total = warmup + steps
+    ctx = lib.Context(0)
+    lib.mppi_reserve(ctx, max(sc.K for sc in fleet), max(sc.N for sc in fleet),
+                     max(sc.M for sc in fleet))
+    dev = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda")
+    insts = []
+    for sc in fleet:
+        insts.append(dict(sc=sc, x_hat=dev(sc.x0), x_ref=dev(sc.x_ref(0)),
+                          obs=lib.obstacles_to_device(sc.obstacles), u0=dev(sc.u_nom0()),
+                          u_apply=torch.empty(8, device="cuda"),
+                          diag=lib.new_diag()))
+    for it in insts:
+        it["u_nom"] = it["u0"].clone()
+
+    def requests(t):
+        return lib.make_requests([dict(veh=it["sc"].veh, cost=it["sc"].cost, solve=it["sc"].solve(t),
+                                       x_hat=it["x_hat"], x_ref=it["x_ref"], obs=it["obs"],
+                                       M=it["sc"].M, u_nom=it["u_nom"], u_apply=it["u_apply"],
+                                       diag=it["diag"]) for it in insts])
+
+    reqs = [requests(t) for t in range(total)]
+    lib.mppi_batch_reserve(ctx, reqs[0])
+    cfg = lib.mppi_batch_autotune(ctx, reqs[0], reps=1) if args.autotune else \
+        lib.mppi_batch_get_config(ctx)
+    log(f"bench: batched launch shape {cfg}")
+    steps_per_batch = sum(sc.K * sc.N for sc in fleet)
+    flop_per_batch = sum(rollout_flop_per_launch(sc.K, sc.N, sc.M) for sc in fleet)
+    stream = torch.cuda.current_stream()
+
+    for t in range(warmup):
+        lib.mppi_batch_update(ctx, reqs[t], stream=stream)
+    torch.cuda.synchronize()
+    lat = []
+    t_start = time.perf_counter()
+    for t in range(warmup, total):
+        t0 = time.perf_counter()
+        lib.mppi_batch_update(ctx, reqs[t], stream=stream)
+        stream.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    t_end = time.perf_counter()
+    batched = steps_per_batch * steps / (t_end - t_start)
+
+    # kernel time of the rollout stage: a profiled pass (events around the stage)
+    lib.mppi_profile_enable(ctx, True)
+    lib.mppi_profile_read(ctx)
+    for t in range(min(steps, 5)):
+        lib.mppi_batch_update(ctx, reqs[t], stream=stream)
+    torch.cuda.synchronize()
+    prof = lib.mppi_profile_read(ctx)
+    lib.mppi_profile_enable(ctx, False)
+    rollout_ms = prof["batch_rollout_ms"] / max(1, prof["batches"])
+    rest_ms = prof["batch_rest_ms"] / max(1, prof["batches"])
+    du_bytes = sum(reduction_bytes_per_launch(sc.K, sc.N) for sc in fleet)
+
+    # the same updates as sequential one-instance launch sequences
+    for it in insts:
+        it["u_nom"].copy_(it["u0"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(plain_steps):
+        for it in insts:
+            sc = it["sc"]
+            lib.mppi_update(ctx, sc.veh, sc.cost, sc.solve(t), it["x_hat"], it["x_ref"], it["obs"],
+                            sc.M, it["u_nom"], it["u_apply"], it["diag"], stream=stream)
+        stream.synchronize()
+    plain = steps_per_batch * plain_steps / (time.perf_counter() - t0)
+    statuses = [lib.diag_from_tensor(it["diag"])["status"] for it in insts]
+    ctx.close()
+    if any(s != 0 for s in statuses):
+        raise RuntimeError(f"batched updates failed on device: {statuses}")
+    achieved = flop_per_batch / (rollout_ms * 1e-3)
+    return {
+        "workload": f"c4_batch: {len(fleet)} vehicles, K in {{1024..16384}}, N in [50, 200], "
+                    f"0-200 spheres; one persistent hipGraph launch per batch",
+        "rollout_steps_per_batch": steps_per_batch,
+        "value": batched, "unit": "rollout-steps/s", "steps": steps,
+        "ms_per_batch": (t_end - t_start) / steps * 1e3,
+        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
+        "plain_sequential": {"value": plain, "unit": "rollout-steps/s", "steps": plain_steps},
+        "speedup_vs_plain": batched / plain,
+        "launch": cfg,
+        "device_ms_per_batch": {"rollout": rollout_ms, "weights_sum_apply": rest_ms},
+        "roofline": {"kernel": "batch_rollout_kernel", "bound": "alu",
+                     "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
+                     "frac_of_unpacked_peak": achieved / PEAK_FP32_UNPACKED,
+                     "flop_per_launch": flop_per_batch},
+        "reduction_stages": {"bytes_per_batch": du_bytes,
+                             "achieved": du_bytes / (rest_ms * 1e-3) / 1e9, "unit": "GB/s",
+                             "note": "weights + weighted sum + apply, bytes of the weighted sum"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--batched-steps", type=int, default=20,
+                    help="batched updates of the 256-vehicle mix timed beside the plain line "
+                         "(0 skips the batched leg)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="use the library's default rollout launch shape")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -301,7 +408,17 @@ def main():
               "(the MPPI update of one vehicle runs on one device; see the design notes "
               "on sharding vehicles or samples over several GPUs).", file=sys.stderr)
         sys.exit(2)
-    out = run(args)
+    if args.config == "c4":
+        b = run_batched(args, args.steps, args.warmup, plain_steps=2)
+        out = {"metric": METRIC, "value": b["value"], "unit": "rollout-steps/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": b["ms_per_batch"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+               "data": "synthetic", "config": {"workload": b["workload"]},
+               "roofline": b["roofline"], "batched": b}
+    else:
+        out = run(args)
+        if args.batched_steps > 0:
+            out["batched"] = run_batched(args, args.batched_steps, 3, plain_steps=2)
     print(json.dumps(out), flush=True)
 
 

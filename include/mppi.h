@@ -232,13 +232,68 @@ mppi_status mppi_autotune(mppi_ctx *ctx, void *stream, const mppi_vehicle *veh,
                           const float *x_ref, const mppi_obstacle *obs, int32_t M,
                           const float *u_nom, int32_t reps, mppi_launch_config *best);
 
+/* --- batched updates ------------------------------------------------------------ */
+
+/* One instance of a batch: its own model, cost, problem and device buffers (the same
+ * meaning and layouts as the arguments of mppi_update).  diag may be NULL. */
+typedef struct mppi_request {
+    mppi_vehicle veh;
+    mppi_cost cost;
+    mppi_solve solve;
+    const float *x_hat;
+    const float *x_ref;
+    const mppi_obstacle *obs;
+    int32_t M;
+    float *u_nom;
+    float *u_apply;
+    mppi_diag *diag;
+} mppi_request;
+
+/* Launch shape of the batched rollout: workgroup size (64, 128, 256), lanes per
+ * sample (1, 2, 4, 8; must divide block), obstacle-loop unroll (1, 4), persistent
+ * workgroups per compute unit (1..16), and whether to replay a captured HIP graph
+ * (1) or launch the kernels one by one (0). */
+typedef struct mppi_batch_config {
+    int32_t block;
+    int32_t lanes;
+    int32_t unroll;
+    int32_t blocks_per_cu;
+    int32_t use_graph;
+} mppi_batch_config;
+
+/* Grow the batch scratch (delta_u, costs, weights, descriptors, work queue) to hold
+ * this list of requests.  The only batch call that allocates; synchronises the device
+ * when it grows. */
+mppi_status mppi_batch_reserve(mppi_ctx *ctx, const mppi_request *reqs, int32_t n);
+
+/* MPPI updates of n independent instances with uneven K, N and M in one launch
+ * sequence on `stream` (Algorithm 1 loop body for each; the same results, bit for
+ * bit, as mppi_update with the same lanes per sample).  A persistent rollout kernel
+ * takes (instance, sample tile) items longest first from a device queue; weights,
+ * weighted sums and shifts follow per instance.  With use_graph the sequence is a HIP
+ * graph captured once per launch shape and replayed.  Host-side planning is copied
+ * from pinned memory on `stream`; the call waits only for the previous batch's copy.
+ * MPPI_E_CAPACITY if the list does not fit the reserved scratch. */
+mppi_status mppi_batch_update(mppi_ctx *ctx, void *stream, const mppi_request *reqs, int32_t n);
+
+/* Time every batched launch shape on this list (reps rollout passes each), keep the
+ * fastest as the context's batch shape and return it.  Synchronises the stream. */
+mppi_status mppi_batch_autotune(mppi_ctx *ctx, void *stream, const mppi_request *reqs, int32_t n,
+                                int32_t reps, mppi_batch_config *best);
+mppi_status mppi_batch_get_config(const mppi_ctx *ctx, mppi_batch_config *out);
+mppi_status mppi_batch_set_config(mppi_ctx *ctx, const mppi_batch_config *cfg);
+
 /* --- profiling ---------------------------------------------------------------- */
 
-/* Per-kernel device time of mppi_update, measured with HIP events on the
- * update's stream while enabled. */
+/* Per-kernel device time of mppi_update, and of mppi_batch_update's rollout stage and
+ * remaining stages, measured with HIP events on the call's stream while enabled.
+ * While profiling, batches are launched kernel by kernel (no graph replay) so that
+ * the events can bracket the rollout stage. */
 typedef struct mppi_profile {
     int64_t updates;
     double rollout_ms, weights_ms, reduce_ms, apply_ms;
+    int64_t batches;
+    double batch_rollout_ms, batch_rest_ms;
 } mppi_profile;
 
 mppi_status mppi_profile_enable(mppi_ctx *ctx, int32_t on);

@@ -68,9 +68,21 @@ class LaunchConfig(C.Structure):
     _fields_ = [("block", C.c_int32), ("lanes", C.c_int32), ("unroll", C.c_int32)]
 
 
+class Request(C.Structure):
+    _fields_ = [("veh", Vehicle), ("cost", Cost), ("solve", Solve), ("x_hat", C.c_void_p),
+                ("x_ref", C.c_void_p), ("obs", C.c_void_p), ("M", C.c_int32),
+                ("u_nom", C.c_void_p), ("u_apply", C.c_void_p), ("diag", C.c_void_p)]
+
+
+class BatchConfig(C.Structure):
+    _fields_ = [("block", C.c_int32), ("lanes", C.c_int32), ("unroll", C.c_int32),
+                ("blocks_per_cu", C.c_int32), ("use_graph", C.c_int32)]
+
+
 class Profile(C.Structure):
     _fields_ = [("updates", C.c_int64), ("rollout_ms", C.c_double), ("weights_ms", C.c_double),
-                ("reduce_ms", C.c_double), ("apply_ms", C.c_double)]
+                ("reduce_ms", C.c_double), ("apply_ms", C.c_double), ("batches", C.c_int64),
+                ("batch_rollout_ms", C.c_double), ("batch_rest_ms", C.c_double)]
 
 
 OBSTACLE_DTYPE = np.dtype([("type", "<i4"), ("c", "<f4", (3,)), ("r", "<f4")])
@@ -102,6 +114,11 @@ _SIGS = {
     "mppi_set_config": [_vp, _i32, _i32, _i32, C.POINTER(LaunchConfig)],
     "mppi_autotune": [_vp, _vp, _PV, _PC, _PS, _vp, _vp, _vp, _i32, _vp, _i32,
                       C.POINTER(LaunchConfig)],
+    "mppi_batch_reserve": [_vp, C.POINTER(Request), _i32],
+    "mppi_batch_update": [_vp, _vp, C.POINTER(Request), _i32],
+    "mppi_batch_autotune": [_vp, _vp, C.POINTER(Request), _i32, _i32, C.POINTER(BatchConfig)],
+    "mppi_batch_get_config": [_vp, C.POINTER(BatchConfig)],
+    "mppi_batch_set_config": [_vp, C.POINTER(BatchConfig)],
     "mppi_profile_enable": [_vp, _i32],
     "mppi_profile_read": [_vp, C.POINTER(Profile)],
 }
@@ -308,6 +325,53 @@ def mppi_autotune(ctx, veh, cst, slv, x_hat, x_ref, obs_dev, M, u_nom, reps=3, s
     return dict(block=best.block, lanes=best.lanes, unroll=best.unroll)
 
 
+def make_requests(items) -> C.Array:
+    """items: dicts with veh, cost, solve (parameter dicts) and device tensors x_hat,
+    x_ref, obs (may be None when M = 0), M, u_nom, u_apply and optionally diag."""
+    arr = (Request * len(items))()
+    for r, it in zip(arr, items):
+        r.veh, r.cost, r.solve = vehicle(it["veh"]), cost(it["cost"]), solve(it["solve"])
+        r.x_hat, r.x_ref = it["x_hat"].data_ptr(), it["x_ref"].data_ptr()
+        r.M = int(it["M"])
+        r.obs = it["obs"].data_ptr() if r.M > 0 else None
+        r.u_nom, r.u_apply = it["u_nom"].data_ptr(), it["u_apply"].data_ptr()
+        d = it.get("diag")
+        r.diag = d.data_ptr() if d is not None else None
+    return arr
+
+
+def mppi_batch_reserve(ctx, reqs):
+    ctx.check(_lib.mppi_batch_reserve(ctx.handle, reqs, len(reqs)), "mppi_batch_reserve")
+
+
+def mppi_batch_update(ctx, reqs, stream=None):
+    ctx.check(_lib.mppi_batch_update(ctx.handle, _stream(stream), reqs, len(reqs)),
+              "mppi_batch_update")
+
+
+def _batch_cfg_dict(c):
+    return dict(block=c.block, lanes=c.lanes, unroll=c.unroll, blocks_per_cu=c.blocks_per_cu,
+                use_graph=c.use_graph)
+
+
+def mppi_batch_autotune(ctx, reqs, reps=2, stream=None) -> dict:
+    best = BatchConfig()
+    ctx.check(_lib.mppi_batch_autotune(ctx.handle, _stream(stream), reqs, len(reqs), int(reps),
+                                       C.byref(best)), "mppi_batch_autotune")
+    return _batch_cfg_dict(best)
+
+
+def mppi_batch_get_config(ctx) -> dict:
+    c = BatchConfig()
+    ctx.check(_lib.mppi_batch_get_config(ctx.handle, C.byref(c)), "mppi_batch_get_config")
+    return _batch_cfg_dict(c)
+
+
+def mppi_batch_set_config(ctx, block, lanes, unroll, blocks_per_cu, use_graph=True):
+    c = BatchConfig(int(block), int(lanes), int(unroll), int(blocks_per_cu), 1 if use_graph else 0)
+    ctx.check(_lib.mppi_batch_set_config(ctx.handle, C.byref(c)), "mppi_batch_set_config")
+
+
 def mppi_profile_enable(ctx, on=True):
     ctx.check(_lib.mppi_profile_enable(ctx.handle, 1 if on else 0), "mppi_profile_enable")
 
@@ -316,7 +380,8 @@ def mppi_profile_read(ctx) -> dict:
     p = Profile()
     ctx.check(_lib.mppi_profile_read(ctx.handle, C.byref(p)), "mppi_profile_read")
     return dict(updates=p.updates, rollout_ms=p.rollout_ms, weights_ms=p.weights_ms,
-                reduce_ms=p.reduce_ms, apply_ms=p.apply_ms)
+                reduce_ms=p.reduce_ms, apply_ms=p.apply_ms, batches=p.batches,
+                batch_rollout_ms=p.batch_rollout_ms, batch_rest_ms=p.batch_rest_ms)
 
 
 def mppi_status_str(st: int) -> str:

@@ -10,8 +10,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "api.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("kernels.h", "model.h")] + [
+SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "batch.hip", "api.hip", "batch_api.hip")]
+HEADERS = [os.path.join(CSRC, f) for f in ("kernels.h", "model.h", "stages.h", "batch.h",
+                                           "context.h")] + [
     os.path.join(ROOT, "include", "mppi.h")]
 LIB = os.path.join(HERE, "libmppi.so")
 ARCH = os.environ.get("MPPI_OFFLOAD_ARCH", "gfx950")

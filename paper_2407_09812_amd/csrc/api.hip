@@ -11,29 +11,12 @@
 #include <tuple>
 #include <vector>
 
+#include "context.h"
 #include "kernels.h"
 
 using namespace mppi;
 
-struct mppi_ctx {
-    int device = 0;
-    int K_cap = 0, N_cap = 0, M_cap = 0, ld = 0;
-    float* du = nullptr;        // [N_cap][4][ld]
-    float* S = nullptr;         // [ld]
-    float* w = nullptr;         // [ld]
-    float* u_upd = nullptr;     // [N_cap][4]
-    mppi_diag* diag = nullptr;  // 1
-    std::map<std::tuple<int, int, int>, LaunchConfig> tuned;   // size class -> shape
-    std::string last_error;
-    // profiling: 5 events per update bracket rollout, weights, sum, apply
-    bool profiling = false;
-    std::vector<hipEvent_t> pool, pending;
-    mppi_profile acc{};
-};
-
-namespace {
-
-constexpr int kEventsPerUpdate = 5;
+namespace mppi {
 
 mppi_status fail(mppi_ctx* ctx, mppi_status s, const std::string& msg)
 {
@@ -45,12 +28,6 @@ mppi_status hip_fail(mppi_ctx* ctx, hipError_t e, const char* where)
 {
     return fail(ctx, MPPI_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
-
-#define HIP_TRY(ctx, expr)                                   \
-    do {                                                     \
-        hipError_t e_ = (expr);                              \
-        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
-    } while (0)
 
 bool finite_all(const float* v, int n)
 {
@@ -155,6 +132,12 @@ RolloutArgs rollout_args(const mppi_vehicle& v, const mppi_cost& c, const mppi_s
     return a;
 }
 
+}  // namespace mppi
+
+namespace {
+
+constexpr int kEventsPerUpdate = 5;
+
 void free_scratch(mppi_ctx* ctx)
 {
     (void)hipFree(ctx->du); (void)hipFree(ctx->S); (void)hipFree(ctx->w);
@@ -196,7 +179,9 @@ LaunchConfig config_for(const mppi_ctx* ctx, int K, int N, int M)
     return it != ctx->tuned.end() ? it->second : heuristic_config(K, M);
 }
 
-hipEvent_t take_event(mppi_ctx* ctx)
+}  // namespace
+
+hipEvent_t mppi::take_event(mppi_ctx* ctx)
 {
     if (!ctx->pool.empty()) {
         hipEvent_t e = ctx->pool.back();
@@ -207,8 +192,6 @@ hipEvent_t take_event(mppi_ctx* ctx)
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
 }
-
-}  // namespace
 
 extern "C" {
 
@@ -253,7 +236,9 @@ mppi_status mppi_create(int device, mppi_ctx** out)
     mppi_ctx* ctx = new (std::nothrow) mppi_ctx();
     if (!ctx) return MPPI_E_OOM;
     ctx->device = device;
-    if (hipSetDevice(device) != hipSuccess) {
+    if (hipSetDevice(device) != hipSuccess ||
+        hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, device) !=
+            hipSuccess) {
         delete ctx;
         return MPPI_E_HIP;
     }
@@ -267,8 +252,10 @@ mppi_status mppi_destroy(mppi_ctx* ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     free_scratch(ctx);
+    free_batch(ctx);
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->pending) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->batch_pending) (void)hipEventDestroy(e);
     delete ctx;
     return MPPI_OK;
 }
@@ -525,6 +512,18 @@ mppi_status mppi_profile_read(mppi_ctx* ctx, mppi_profile* out)
     }
     for (hipEvent_t e : ctx->pending) ctx->pool.push_back(e);
     ctx->pending.clear();
+    for (size_t b = 0; b + 3 <= ctx->batch_pending.size(); b += 3) {
+        hipEvent_t* e = &ctx->batch_pending[b];
+        HIP_TRY(ctx, hipEventSynchronize(e[2]));
+        float t0 = 0.0f, t1 = 0.0f;
+        HIP_TRY(ctx, hipEventElapsedTime(&t0, e[0], e[1]));
+        HIP_TRY(ctx, hipEventElapsedTime(&t1, e[1], e[2]));
+        ctx->acc.batches += 1;
+        ctx->acc.batch_rollout_ms += t0;
+        ctx->acc.batch_rest_ms += t1;
+    }
+    for (hipEvent_t e : ctx->batch_pending) ctx->pool.push_back(e);
+    ctx->batch_pending.clear();
     *out = ctx->acc;
     ctx->acc = mppi_profile{};
     return MPPI_OK;

@@ -1,0 +1,146 @@
+// Batched MPPI kernels: many uneven instances (K, N, M differ) in one launch sequence.
+//
+//   batch_reset_kernel     work-queue head <- 0 (a kernel, so the sequence can be
+//                          captured in a HIP graph without memset nodes)
+//   batch_rollout_kernel   persistent: each workgroup pulls (instance, sample tile)
+//                          items, longest first, from a device queue, stages that
+//                          instance's obstacles in LDS and rolls the tile out
+//   batch_weights_kernel   one 1024-thread workgroup per instance
+//   batch_wsum_kernel      persistent over all instances' delta_u rows
+//   batch_apply_kernel     one workgroup per instance
+// Every stage calls the same device bodies as the one-instance kernels, so an
+// instance's results are bit-identical alone and inside a batch (for the same
+// lanes-per-sample).
+#include <hip/hip_runtime.h>
+
+#include "batch.h"
+#include "stages.h"
+
+namespace mppi {
+
+__global__ void batch_reset_kernel(BatchHeader* hdr)
+{
+    if (threadIdx.x == 0) hdr->next_item = 0u;
+}
+
+template <int L, int U>
+__global__ __launch_bounds__(256) void batch_rollout_kernel(BatchHeader* hdr,
+                                                           const InstanceDesc* __restrict__ descs,
+                                                           const WorkItem* __restrict__ items)
+{
+    extern __shared__ float4 obs_lds[];
+    __shared__ int s_item;
+    const int n_items = __builtin_amdgcn_readfirstlane(hdr->n_items);
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&hdr->next_item, 1u);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();                       // s_item is rewritten next iteration
+        if (it >= n_items) return;             // uniform: every wave leaves together
+        const int inst = __builtin_amdgcn_readfirstlane(items[it].inst);
+        const int k0 = __builtin_amdgcn_readfirstlane(items[it].k0);
+        const InstanceDesc& D = descs[inst];
+        stage_obstacles(obs_lds, D.obs, D.rp.M, D.x_hat[0], D.x_hat[1], D.x_hat[2],
+                        D.rp.cp.margin);
+        __syncthreads();
+        const int k = k0 + (int)threadIdx.x / L, q = (int)threadIdx.x % L;
+        if (k < D.rp.K) {
+            if (D.rp.mp.lag)
+                rollout_sample<L, U, true, false>(D.rp, D.x_hat, D.x_ref, D.u_nom, D.du, D.S,
+                                                  nullptr, obs_lds, k, q);
+            else
+                rollout_sample<L, U, false, false>(D.rp, D.x_hat, D.x_ref, D.u_nom, D.du, D.S,
+                                                   nullptr, obs_lds, k, q);
+        }
+        __syncthreads();                       // LDS is restaged for the next item
+    }
+}
+
+__global__ __launch_bounds__(kWeightsThreads) void batch_weights_kernel(
+    const BatchHeader* __restrict__ hdr, const InstanceDesc* __restrict__ descs)
+{
+    const int i = blockIdx.x;
+    if (i >= hdr->n_inst) return;
+    const InstanceDesc& D = descs[i];
+    weights_block(D.S, D.rp.K, D.lambda, D.w, D.diag);
+}
+
+__global__ __launch_bounds__(kSumThreads) void batch_wsum_kernel(const BatchHeader* __restrict__ hdr,
+                                                                 const InstanceDesc* __restrict__ descs)
+{
+    const int n_rows = hdr->n_rows, n_inst = hdr->n_inst;
+    for (int r = blockIdx.x; r < n_rows; r += gridDim.x) {
+        int lo = 0, hi = n_inst - 1;           // last instance whose rows start at or before r
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (descs[mid].row0 <= r) lo = mid; else hi = mid - 1;
+        }
+        const InstanceDesc& D = descs[lo];
+        weighted_sum_row(D.w, D.du, D.rp.K, D.rp.ld, D.u_nom, D.u_upd, D.diag, r - D.row0);
+    }
+}
+
+__global__ void batch_apply_kernel(const BatchHeader* __restrict__ hdr,
+                                   const InstanceDesc* __restrict__ descs)
+{
+    const int i = blockIdx.x;
+    if (i >= hdr->n_inst) return;
+    const InstanceDesc& D = descs[i];
+    apply_shift_block(D.rp.mp, D.x_hat, D.u_upd, D.u_nom, D.u_apply, D.rp.N,
+                      make_float4(D.u_init[0], D.u_init[1], D.u_init[2], D.u_init[3]), D.diag);
+}
+
+// ---------------------------------------------------------------------------
+
+bool valid_batch_launch(const BatchLaunch& c)
+{
+    return (c.block == 64 || c.block == 128 || c.block == 256) &&
+           (c.lanes == 1 || c.lanes == 2 || c.lanes == 4 || c.lanes == 8) &&
+           (c.unroll == 1 || c.unroll == 4) && c.blocks_per_cu >= 1 && c.blocks_per_cu <= 16 &&
+           c.block % c.lanes == 0;
+}
+
+hipError_t launch_batch_rollout(BatchHeader* hdr, const InstanceDesc* descs, const WorkItem* items,
+                                int cu_count, int lds_bytes, const BatchLaunch& c,
+                                hipStream_t stream)
+{
+    if (!valid_batch_launch(c)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, stream, hdr);
+    const dim3 grid(cu_count * c.blocks_per_cu), block(c.block);
+#define MPPI_BATCH_ROLLOUT(L, U) \
+    hipLaunchKernelGGL((batch_rollout_kernel<L, U>), grid, block, lds_bytes, stream, hdr, descs, items)
+    switch (c.lanes * 10 + c.unroll) {
+    case 11: MPPI_BATCH_ROLLOUT(1, 1); break;
+    case 14: MPPI_BATCH_ROLLOUT(1, 4); break;
+    case 21: MPPI_BATCH_ROLLOUT(2, 1); break;
+    case 24: MPPI_BATCH_ROLLOUT(2, 4); break;
+    case 41: MPPI_BATCH_ROLLOUT(4, 1); break;
+    case 44: MPPI_BATCH_ROLLOUT(4, 4); break;
+    case 81: MPPI_BATCH_ROLLOUT(8, 1); break;
+    default: MPPI_BATCH_ROLLOUT(8, 4); break;
+    }
+#undef MPPI_BATCH_ROLLOUT
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(BatchHeader* hdr, const InstanceDesc* descs, const WorkItem* items,
+                        int n_cap, int cu_count, int lds_bytes, const BatchLaunch& c,
+                        hipStream_t stream)
+{
+    hipError_t e = launch_batch_rollout(hdr, descs, items, cu_count, lds_bytes, c, stream);
+    if (e != hipSuccess) return e;
+    return launch_batch_tail(hdr, descs, n_cap, cu_count, stream);
+}
+
+hipError_t launch_batch_tail(BatchHeader* hdr, const InstanceDesc* descs, int n_cap, int cu_count,
+                             hipStream_t stream)
+{
+    hipLaunchKernelGGL(batch_weights_kernel, dim3(n_cap), dim3(kWeightsThreads), 0, stream, hdr,
+                       descs);
+    hipLaunchKernelGGL(batch_wsum_kernel, dim3(cu_count * 8), dim3(kSumThreads), 0, stream, hdr,
+                       descs);
+    hipLaunchKernelGGL(batch_apply_kernel, dim3(n_cap), dim3(256), 0, stream, hdr, descs);
+    return hipGetLastError();
+}
+
+}  // namespace mppi

@@ -8,12 +8,9 @@
 
 namespace mppi {
 
-constexpr int kWeightsThreads = 1024;
-constexpr int kSumThreads = 256;
-
-// Arguments of the rollout kernel.  The read-only inputs travel as separate
-// __restrict__ kernel arguments so that their wave-uniform rows are fetched with
-// scalar loads.
+// Arguments of one rollout launch (host side).  The kernel receives the scalar part
+// by value and the read-only inputs as separate __restrict__ arguments, so that their
+// wave-uniform rows are fetched with scalar loads.
 struct RolloutArgs {
     ModelParams mp;
     CostParams cp;
@@ -30,13 +27,6 @@ struct RolloutArgs {
     float* states;               // [N+1][17][ld] or nullptr
 };
 
-// The scalar part of RolloutArgs, passed by value.
-struct RolloutParams {
-    ModelParams mp;
-    CostParams cp;
-    NoiseParams np;
-    int M, K, N, ld;
-};
 
 // Rollout launch shape: `lanes` consecutive lanes per sample (the obstacle tests are
 // divided among them), `block` threads per workgroup, obstacle loop unrolled `unroll`.

@@ -1,6 +1,6 @@
-// MPPI kernels for gfx950 (wave64, CDNA4).
+// One-instance MPPI kernels for gfx950 (wave64, CDNA4).
 //
-//   rollout_kernel      one lane per sample: in-register Philox noise, rate
+//   rollout_kernel      one sample per L lanes: in-register Philox noise, rate
 //                       controller, RK4 of the 17-value state, tracking and
 //                       obstacle cost (obstacles staged in LDS)        Eqs. (2)-(3)
 //   weights_kernel      one workgroup: wave-shuffle min, compensated
@@ -12,16 +12,10 @@
 //   noise_kernel, philox_kernel   the rollout's noise on its own (checks)
 #include <hip/hip_runtime.h>
 
-#include <climits>
-#include <cmath>
-
 #include "kernels.h"
+#include "stages.h"
 
 namespace mppi {
-
-// ---------------------------------------------------------------------------
-// G1: rollouts and costs
-// ---------------------------------------------------------------------------
 
 template <int L, int U, bool kLag, bool kDump>
 __global__ __launch_bounds__(256) void rollout_kernel(
@@ -30,259 +24,27 @@ __global__ __launch_bounds__(256) void rollout_kernel(
     float* __restrict__ du_out, float* __restrict__ S_out, float* __restrict__ states)
 {
     extern __shared__ float4 obs_lds[];   // 2 x M float4
-    const float phx = x_hat[0], phy = x_hat[1], phz = x_hat[2];
-
-    // Stage the obstacle list once per workgroup, centred on x_hat's position:
-    // the rollouts integrate positions relative to p_hat, which keeps binary32
-    // rounding at the scale of the excursion rather than of the world frame.
-    for (int i = threadIdx.x; i < a.M; i += blockDim.x) {
-        const mppi_obstacle o = obs[i];
-        const float R = o.r + a.cp.margin;
-        obs_lds[2 * i] = make_float4(o.c[0] - phx, o.c[1] - phy, o.c[2] - phz,
-                                     o.type == MPPI_VCYLINDER ? 0.0f : 1.0f);
-        obs_lds[2 * i + 1] = make_float4(o.r * o.r, R * R, R, 0.0f);
-    }
+    stage_obstacles(obs_lds, obs, a.M, x_hat[0], x_hat[1], x_hat[2], a.cp.margin);
     __syncthreads();
-
-    // L consecutive lanes integrate the same sample (identical instructions and
-    // operands, hence identical trajectories); lane q = 0 of the group writes.
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = g / L, q = g % L;
     if (k >= a.K) return;
-    const bool writer = (q == 0);
-    const size_t ld = (size_t)a.ld;
-
-    State x;
-    x.px = 0.0f; x.py = 0.0f; x.pz = 0.0f;
-    x.qw = x_hat[3]; x.qx = x_hat[4]; x.qy = x_hat[5]; x.qz = x_hat[6];
-    x.vx = x_hat[7]; x.vy = x_hat[8]; x.vz = x_hat[9];
-    x.wx = x_hat[10]; x.wy = x_hat[11]; x.wz = x_hat[12];
-    x.T0 = x_hat[13]; x.T1 = x_hat[14]; x.T2 = x_hat[15]; x.T3 = x_hat[16];
-
-    if (kDump && writer) {   // trajectories [N+1][17][ld], positions back in the world frame
-        const float vals[17] = {x.px + phx, x.py + phy, x.pz + phz, x.qw, x.qx, x.qy, x.qz,
-                                x.vx, x.vy, x.vz, x.wx, x.wy, x.wz, x.T0, x.T1, x.T2, x.T3};
-#pragma unroll
-        for (int i = 0; i < 17; ++i) states[(size_t)i * ld + k] = vals[i];
-    }
-
-    KahanSum S;
-    // state j = 0 (the estimate itself) is scored like every other state (Eq. (17))
-    S.add(tracking_cost(a.cp, x, x_ref[0] - phx, x_ref[1] - phy, x_ref[2] - phz, x_ref) +
-          obstacle_cost<L, U>(a.cp, x.px, x.py, x.pz, obs_lds, a.M, q));
-
-    float up[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int j = 0; j < a.N; ++j) {
-        float du[4], u[4];
-        draw_noise(a.np, (uint32_t)k, (uint32_t)j, du);
-        if (writer) {
-            float* dst = du_out + (size_t)(4 * j) * ld + k;
-#pragma unroll
-            for (int d = 0; d < 4; ++d) dst[(size_t)d * ld] = du[d];
-        }
-#pragma unroll
-        for (int d = 0; d < 4; ++d) u[d] = u_nom[4 * j + d] + du[d];   // Eq. (2): u = u_nom + du
-        // input and input-change terms of Eq. (16)
-        float cu = 0.0f;
-#pragma unroll
-        for (int d = 0; d < 4; ++d) cu = fmaf(a.cp.R[d] * u[d], u[d], cu);
-        if (j > 0) {
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                const float e = u[d] - up[d];
-                cu = fmaf(a.cp.Rd[d] * e, e, cu);
-            }
-        }
-#pragma unroll
-        for (int d = 0; d < 4; ++d) up[d] = u[d];
-
-        float Tc[4];
-        rate_controller(a.mp, x.wx, x.wy, x.wz, u, Tc);
-        rk4_step<kLag>(a.mp, x, Tc);
-
-        const float* ref = x_ref + (size_t)13 * (j + 1);
-        const float cx = tracking_cost(a.cp, x, ref[0] - phx, ref[1] - phy, ref[2] - phz, ref) +
-                         obstacle_cost<L, U>(a.cp, x.px, x.py, x.pz, obs_lds, a.M, q);
-        S.add(cu + cx);
-
-        if (kDump && writer) {
-            const float vals[17] = {x.px + phx, x.py + phy, x.pz + phz, x.qw, x.qx, x.qy, x.qz,
-                                    x.vx, x.vy, x.vz, x.wx, x.wy, x.wz, x.T0, x.T1, x.T2, x.T3};
-            float* st = states + (size_t)17 * (j + 1) * ld + k;
-#pragma unroll
-            for (int i = 0; i < 17; ++i) st[(size_t)i * ld] = vals[i];
-        }
-    }
-    if (writer) S_out[k] = S.s;
+    rollout_sample<L, U, kLag, kDump>(a, x_hat, x_ref, u_nom, du_out, S_out, states, obs_lds, k, q);
 }
-
-// ---------------------------------------------------------------------------
-// Block reductions (wave64 shuffles, then LDS across waves)
-// ---------------------------------------------------------------------------
-
-// Lexicographic (value, index) minimum; NaN never wins.
-__device__ __forceinline__ void argmin_merge(float& v, int& i, float v2, int i2)
-{
-    if (v2 < v || (v2 == v && i2 < i)) { v = v2; i = i2; }
-}
-
-// Error-free sum of two compensated pairs (Knuth two-sum).
-__device__ __forceinline__ void twosum_merge(float& s, float& c, float s2, float c2)
-{
-    const float t = s + s2;
-    const float bp = t - s;
-    const float e = (s - (t - bp)) + (s2 - bp);
-    s = t;
-    c = c + c2 + e;
-}
-
-// ---------------------------------------------------------------------------
-// G2: softmin weights
-// ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kWeightsThreads) void weights_kernel(const float* __restrict__ S, int K,
                                                                  float lambda, float* __restrict__ w,
                                                                  mppi_diag* __restrict__ diag)
 {
-    __shared__ float sh_v[kWeightsThreads / 64];
-    __shared__ int sh_i[kWeightsThreads / 64], sh_n[kWeightsThreads / 64];
-    __shared__ float sh_s[kWeightsThreads / 64], sh_c[kWeightsThreads / 64], sh_q[kWeightsThreads / 64];
-    __shared__ float bc_rho;
-    __shared__ int bc_n;
-    __shared__ float bc_eta;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
-
-    // rho = min over finite costs, its first index, and the finite count
-    float mv = INFINITY;
-    int mi = INT_MAX, nf = 0;
-    for (int k = tid; k < K; k += blockDim.x) {
-        const float s = S[k];
-        if (isfinite(s)) {
-            ++nf;
-            if (s < mv) { mv = s; mi = k; }
-        }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const float v2 = __shfl_xor(mv, off);
-        const int i2 = __shfl_xor(mi, off);
-        argmin_merge(mv, mi, v2, i2);
-        nf += __shfl_xor(nf, off);
-    }
-    if (lane == 0) { sh_v[wv] = mv; sh_i[wv] = mi; sh_n[wv] = nf; }
-    __syncthreads();
-    if (tid == 0) {
-        float v = sh_v[0];
-        int i = sh_i[0], n = sh_n[0];
-        for (int q = 1; q < nw; ++q) { argmin_merge(v, i, sh_v[q], sh_i[q]); n += sh_n[q]; }
-        bc_rho = v; bc_n = n;
-        diag->rho = v; diag->argmin = n > 0 ? i : -1; diag->n_finite = n;
-    }
-    __syncthreads();
-    const float rho = bc_rho;
-    if (bc_n == 0) {
-        for (int k = tid; k < K; k += blockDim.x) w[k] = 0.0f;
-        if (tid == 0) {
-            diag->eta = 0.0f; diag->ess = 0.0f; diag->status = MPPI_E_ALL_NONFINITE;
-        }
-        return;
-    }
-
-    // e_k = exp(-(S_k - rho) / lambda) = 2^((rho - S_k) log2(e) / lambda); eta = sum_k e_k
-    const float scale = 1.44269504089f / lambda;
-    float es = 0.0f, ec = 0.0f, q2 = 0.0f;
-    for (int k = tid; k < K; k += blockDim.x) {
-        const float s = S[k];
-        const float e = isfinite(s) ? __builtin_amdgcn_exp2f((rho - s) * scale) : 0.0f;
-        w[k] = e;
-        const float y = e - ec, t = es + y;          // Kahan
-        ec = (t - es) - y;
-        es = t;
-        q2 = fmaf(e, e, q2);
-    }
-    ec = -ec;   // pair (es, ec) with es + ec the compensated value
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const float s2 = __shfl_xor(es, off), c2 = __shfl_xor(ec, off);
-        twosum_merge(es, ec, s2, c2);
-        q2 += __shfl_xor(q2, off);
-    }
-    if (lane == 0) { sh_s[wv] = es; sh_c[wv] = ec; sh_q[wv] = q2; }
-    __syncthreads();
-    if (tid == 0) {
-        float s = sh_s[0], c = sh_c[0], q = sh_q[0];
-        for (int i = 1; i < nw; ++i) { twosum_merge(s, c, sh_s[i], sh_c[i]); q += sh_q[i]; }
-        const float eta = s + c;
-        bc_eta = eta;
-        diag->eta = eta;
-        diag->ess = eta * eta / q;
-        diag->status = MPPI_OK;
-    }
-    __syncthreads();
-    const float inv_eta = 1.0f / bc_eta;
-    for (int k = tid; k < K; k += blockDim.x) w[k] *= inv_eta;
+    weights_block(S, K, lambda, w, diag);
 }
-
-// ---------------------------------------------------------------------------
-// G3: weighted sum of the perturbations, one workgroup per (j, d) row
-// ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kSumThreads) void weighted_sum_kernel(
     const float* __restrict__ w, const float* __restrict__ du, int K, int ld,
     const float* __restrict__ u_in, float* __restrict__ u_out, const mppi_diag* __restrict__ diag)
 {
-    __shared__ float sh[kSumThreads / 64];
-    const int row = blockIdx.x, tid = threadIdx.x;
-    const float* src = du + (size_t)row * ld;
-    float acc = 0.0f;
-    if ((ld & 3) == 0) {
-        const int K4 = K >> 2;
-        const float4* s4 = reinterpret_cast<const float4*>(src);
-        const float4* w4 = reinterpret_cast<const float4*>(w);
-        for (int i = tid; i < K4; i += blockDim.x) {
-            const float4 a = s4[i], b = w4[i];
-            acc = fmaf(a.x, b.x, acc);
-            acc = fmaf(a.y, b.y, acc);
-            acc = fmaf(a.z, b.z, acc);
-            acc = fmaf(a.w, b.w, acc);
-        }
-        for (int k = 4 * K4 + tid; k < K; k += blockDim.x) acc = fmaf(src[k], w[k], acc);
-    } else {
-        for (int k = tid; k < K; k += blockDim.x) acc = fmaf(src[k], w[k], acc);
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if ((tid & 63) == 0) sh[tid >> 6] = acc;
-    __syncthreads();
-    if (tid == 0) {
-        float t = 0.0f;
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
-        const bool ok = diag == nullptr || diag->status == MPPI_OK;
-        u_out[row] = ok ? u_in[row] + t : u_in[row];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// G4: apply and shift
-// ---------------------------------------------------------------------------
-
-__device__ void feasible_input(const ModelParams& P, const float* x, const float* u, float* out)
-{
-    // Eqs. (12)-(15): clipped thrusts -> [F_clip; tau_clip] -> omega_clip
-    float Tc[4];
-    const float uu[4] = {u[0], u[1], u[2], u[3]};
-    rate_controller(P, x[10], x[11], x[12], uu, Tc);
-    const float s01 = Tc[0] + Tc[1], s23 = Tc[2] + Tc[3], d10 = Tc[1] - Tc[0], d23 = Tc[2] - Tc[3];
-    const float F = s01 + s23;
-    const float tau[3] = {P.s * (d10 + d23), P.s * (d10 - d23), P.c * (s23 - s01)};
-    const float gyr[3] = {P.G[0] * x[11] * x[12], P.G[1] * x[12] * x[10], P.G[2] * x[10] * x[11]};
-    const float lim[3] = {P.w_xy_max, P.w_xy_max, P.w_z_max};
-    out[0] = F;
-    for (int i = 0; i < 3; ++i) {
-        float wc = fmaf((tau[i] - gyr[i]) * P.J_inv[i], P.dt, x[10 + i]);
-        if (lim[i] > 0.0f) wc = clampf(wc, -lim[i], lim[i]);
-        out[1 + i] = wc;
-    }
+    const int row = blockIdx.x;
+    weighted_sum_row(w, du, K, ld, u_in, u_out, diag, row);
 }
 
 __global__ void apply_shift_kernel(ModelParams P, const float* __restrict__ x_hat,
@@ -290,15 +52,7 @@ __global__ void apply_shift_kernel(ModelParams P, const float* __restrict__ x_ha
                                    float* __restrict__ u_apply, int N, float4 u_init,
                                    const mppi_diag* __restrict__ diag)
 {
-    const bool ok = diag == nullptr || diag->status == MPPI_OK;
-    if (threadIdx.x == 0) {
-        for (int d = 0; d < 4; ++d) u_apply[d] = u_upd[d];
-        feasible_input(P, x_hat, u_upd, u_apply + 4);
-    }
-    if (!ok) return;   // all costs non-finite: keep the warm start as it was
-    const float init[4] = {u_init.x, u_init.y, u_init.z, u_init.w};
-    for (int i = threadIdx.x; i < 4 * N; i += blockDim.x)
-        u_nom[i] = i < 4 * (N - 1) ? u_upd[i + 4] : init[i & 3];
+    apply_shift_block(P, x_hat, u_upd, u_nom, u_apply, N, u_init, diag);
 }
 
 // ---------------------------------------------------------------------------

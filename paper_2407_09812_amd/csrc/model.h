@@ -46,6 +46,17 @@ struct NoiseParams {
     uint32_t t, seed_hi;    // counter words 2 and 3
 };
 
+// Scalar parameters of one instance's rollout launch.
+struct RolloutParams {
+    ModelParams mp;
+    CostParams cp;
+    NoiseParams np;
+    int M, K, N, ld;
+};
+
+constexpr int kWeightsThreads = 1024;   // one workgroup computes one instance's weights
+constexpr int kSumThreads = 256;        // one workgroup reduces one delta_u row
+
 // 17 state values held in registers.
 struct State {
     float px, py, pz;

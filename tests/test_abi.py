@@ -52,6 +52,36 @@ def test_struct_layouts():
     assert lib.OBSTACLE_DTYPE.itemsize == 20
 
 
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+def test_struct_layouts_match_the_c_header(tmp_path):
+    """sizeof / offsetof of every ABI struct, compiled from include/mppi.h, equal the
+    binding's ctypes layouts."""
+    import paper_2407_09812_amd as lib
+    structs = {"mppi_vehicle": lib.Vehicle, "mppi_cost": lib.Cost, "mppi_solve": lib.Solve,
+               "mppi_diag": lib.Diag, "mppi_launch_config": lib.LaunchConfig,
+               "mppi_request": lib.Request, "mppi_batch_config": lib.BatchConfig,
+               "mppi_profile": lib.Profile}
+    c_name = {"lam": "lambda"}            # ctypes cannot name a field after a Python keyword
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mppi.h"', "int main(void) {"]
+    for cname, ct in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in ct._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {c_name.get(f, f)}));')
+    lines.append('printf("mppi_obstacle %zu\\n", sizeof(mppi_obstacle)); return 0; }')
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
+                   check=True, capture_output=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                  check=True).stdout.strip().split("\n"))
+    for cname, ct in structs.items():
+        assert int(got[cname]) == C.sizeof(ct), cname
+        for f, _ in ct._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(ct, f).offset, (cname, f)
+    assert int(got["mppi_obstacle"]) == lib.OBSTACLE_DTYPE.itemsize
+
+
 def _good():
     sc = W.c2_line(K=128, N=10)
     return sc.veh, sc.cost, sc.solve(0)
