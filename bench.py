@@ -379,12 +379,90 @@ def run_batched(args, steps: int, warmup: int, plain_steps: int):
     }
 
 
+def run_served(args, duration_s: float, rate_hz: float, batch_cfg=None):
+    """The serving configuration: Poisson arrivals from 512 vehicles, each request with
+    its own K and N, admitted by memory budget and batched continuously by the
+    library's server; latency runs from submit to the result on the host."""
+    import numpy as np
+
+    import paper_2407_09812_amd as lib
+    import workloads as W
+
+    fleet, arrivals = W.c5_arrivals(rate_hz=rate_hz, duration_s=duration_s)
+    dt = fleet[0].dt
+    window = 200                                  # reference rows are reused cyclically
+    rows = [sc.ref.rows(0.0, window + 200, dt).astype(np.float32) for sc in fleet]
+    thrust = [np.float32(sc.ref.thrust(0.0, sc.veh["mass"]) / 4.0) for sc in fleet]
+    obs = [lib.obstacles_host(sc.obstacles) for sc in fleet]
+    veh, cost = fleet[0].veh, fleet[0].cost
+    srv = lib.Server(veh, cost, W.hover_control(veh), n_vehicles=len(fleet), K_max=16384, N_max=200,
+                     M_max=200, n_streams=args.serve_streams, max_batch=64,
+                     budget_bytes=int(args.serve_budget_gib * (1 << 30)))
+    if batch_cfg:
+        srv.set_batch_config(batch_cfg["block"], batch_cfg["lanes"], batch_cfg["unroll"],
+                             batch_cfg["blocks_per_cu"])
+    count = [0] * len(fleet)
+    rng = np.random.default_rng(5)
+
+    def submit(vid, K, N):
+        i = count[vid] % window
+        count[vid] += 1
+        x = np.empty(17, dtype=np.float32)
+        x[:13] = rows[vid][i]
+        x[13:] = thrust[vid]
+        x[:3] += rng.normal(0.0, 0.05, 3).astype(np.float32)
+        return srv.submit(vid, K, N, dt, 1.0, (1.0, 1.0, 1.0, 1.0), 5, x, rows[vid][i:i + N + 1],
+                          obs[vid])
+
+    for vid in range(8):                          # warm-up: graph capture on every slot
+        srv.wait(submit(vid, 1024, 50))
+    srv.drain()
+    tickets = []
+    t_start = time.perf_counter()
+    for (ta, vid, K, N) in arrivals:
+        while True:
+            lag = ta - (time.perf_counter() - t_start)
+            if lag <= 0.0:
+                break
+            if lag > 0.002:
+                time.sleep(lag - 0.001)
+        tickets.append(submit(vid, K, N))
+    late = (time.perf_counter() - t_start) - arrivals[-1][0]
+    srv.drain()
+    t_end = time.perf_counter()
+    res = [srv.poll(t) for t in tickets]
+    stats = srv.stats()
+    srv.close()
+    lat = [1e3 * r["latency_s"] for r in res]
+    bad = sum(1 for r in res if r["status"] != 0)
+    steps = sum(r["K"] * r["N"] for r in res)
+    return {
+        "workload": f"c5_serve: Poisson {rate_hz:.0f} req/s from {len(fleet)} vehicles for "
+                    f"{duration_s:.0f} s, K in {{1024..16384}}, N in [50, 200], 0-200 spheres",
+        "requests": len(res), "failed": bad,
+        "value": steps / (t_end - t_start), "unit": "rollout-steps/s",
+        "offered_rollout_steps_per_s": steps / arrivals[-1][0],
+        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99),
+                       "mean": sum(lat) / len(lat), "max": max(lat)},
+        "batches": stats["batches"], "mean_batch": stats["completed"] / max(1, stats["batches"]),
+        "max_in_flight": stats["max_in_flight"], "device_busy_frac": stats["busy_s"] / (t_end - t_start),
+        "streams": args.serve_streams, "budget_gib": args.serve_budget_gib,
+        "submit_lag_s": late,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="length of the served leg beside the plain line (0 skips it); "
+                         "--config c5 runs the full 60 s")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-streams", type=int, default=2)
+    ap.add_argument("--serve-budget-gib", type=float, default=2.0)
     ap.add_argument("--batched-steps", type=int, default=20,
                     help="batched updates of the 256-vehicle mix timed beside the plain line "
                          "(0 skips the batched leg)")
@@ -408,6 +486,14 @@ def main():
               "(the MPPI update of one vehicle runs on one device; see the design notes "
               "on sharding vehicles or samples over several GPUs).", file=sys.stderr)
         sys.exit(2)
+    if args.config == "c5":
+        sv = run_served(args, 60.0, args.serve_rate)
+        out = {"metric": METRIC, "value": sv["value"], "unit": "rollout-steps/s", "n_gpus": 1,
+               "steps": sv["requests"], "warmup": 8, "ms_per_step": sv["latency_ms"]["mean"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+               "data": "synthetic", "config": {"workload": sv["workload"]}, "served": sv}
+        print(json.dumps(out), flush=True)
+        return
     if args.config == "c4":
         b = run_batched(args, args.steps, args.warmup, plain_steps=2)
         out = {"metric": METRIC, "value": b["value"], "unit": "rollout-steps/s", "n_gpus": 1,
@@ -419,6 +505,9 @@ def main():
         out = run(args)
         if args.batched_steps > 0:
             out["batched"] = run_batched(args, args.batched_steps, 3, plain_steps=2)
+        if args.serve_seconds > 0:
+            out["served"] = run_served(args, args.serve_seconds, args.serve_rate,
+                                       out.get("batched", {}).get("launch"))
     print(json.dumps(out), flush=True)
 
 

@@ -283,6 +283,84 @@ mppi_status mppi_batch_autotune(mppi_ctx *ctx, void *stream, const mppi_request 
 mppi_status mppi_batch_get_config(const mppi_ctx *ctx, mppi_batch_config *out);
 mppi_status mppi_batch_set_config(mppi_ctx *ctx, const mppi_batch_config *cfg);
 
+/* --- serving ---------------------------------------------------------------------- */
+
+/* A request loop for many vehicles (continuous batching).  The server owns each
+ * vehicle's warm-start sequence on the device (N_max x 4 floats, initialised to
+ * u_init) and its update counter t; requests carry the state estimate, reference and
+ * obstacles on the host and are copied at submit.  A worker thread admits queued
+ * requests whenever one of n_streams slots is free and the request fits that slot's
+ * share of budget_bytes (its delta_u, costs, weights and inputs), one request per
+ * vehicle in flight (the next update starts from the previous result), in arrival
+ * order, and launches them as one batch (mppi_batch_update) on the slot's stream;
+ * batches on different slots overlap on the device.  A request with horizon N uses
+ * the first N rows of its vehicle's warm start and shifts them. */
+typedef struct mppi_server mppi_server;
+
+typedef struct mppi_server_cfg {
+    int32_t device;
+    int32_t n_vehicles;
+    int32_t K_max, N_max, M_max;   /* per request                                   */
+    int32_t n_streams;             /* concurrent batches, >= 1                      */
+    int32_t max_batch;             /* requests per batch, >= 1                      */
+    int32_t reserved;
+    int64_t budget_bytes;          /* device scratch for in-flight requests         */
+    mppi_vehicle veh;
+    mppi_cost cost;
+    float u_init[4];
+} mppi_server_cfg;
+
+typedef struct mppi_server_request {
+    uint32_t vehicle_id;           /* < n_vehicles                                  */
+    int32_t K, N, M;
+    float dt, lambda;
+    float sigma[4];
+    uint64_t seed;
+    const float *x_hat;            /* host, 17 floats                               */
+    const float *x_ref;            /* host, (N+1) x 13 floats                       */
+    const mppi_obstacle *obs;      /* host, M obstacles                             */
+} mppi_server_request;
+
+typedef struct mppi_server_result {
+    uint64_t ticket;
+    uint32_t vehicle_id;
+    uint32_t t;                    /* the vehicle's update index this request used  */
+    float u_apply[8];              /* as mppi_update's u_apply                      */
+    mppi_diag diag;
+    double submit_s, launch_s, done_s;   /* server clock, seconds since creation    */
+    int32_t K, N;
+} mppi_server_result;
+
+typedef struct mppi_server_stats {
+    int64_t submitted, completed, batches, rejected;
+    int64_t rollout_steps;         /* sum of K N over completed requests            */
+    int64_t max_in_flight;
+    double busy_s;                 /* time with at least one batch in flight        */
+} mppi_server_stats;
+
+mppi_status mppi_server_create(const mppi_server_cfg *cfg, mppi_server **out);
+/* Waits for queued and in-flight requests, then frees everything. */
+mppi_status mppi_server_destroy(mppi_server *srv);
+/* Shape of the batched launches on every slot (see mppi_batch_config). */
+mppi_status mppi_server_set_batch_config(mppi_server *srv, const mppi_batch_config *cfg);
+/* Queue a request (inputs are copied).  MPPI_E_INVALID_ARG for bad parameters or
+ * sizes above the server's maxima, MPPI_E_BUDGET if it can never fit a slot. */
+mppi_status mppi_server_submit(mppi_server *srv, const mppi_server_request *req,
+                               uint64_t *ticket);
+/* Result of a finished request (then forgotten), or MPPI_E_PENDING. */
+mppi_status mppi_server_poll(mppi_server *srv, uint64_t ticket, mppi_server_result *out);
+/* Block until the request has finished, then as mppi_server_poll. */
+mppi_status mppi_server_wait(mppi_server *srv, uint64_t ticket, mppi_server_result *out);
+/* Block until nothing is queued or in flight. */
+mppi_status mppi_server_drain(mppi_server *srv);
+mppi_status mppi_server_stats_get(mppi_server *srv, mppi_server_stats *out);
+double mppi_server_clock(const mppi_server *srv);
+/* Warm starts and update counters: size = n_vehicles (N_max x 4 floats + 1 uint32).
+ * Both drain first; restore makes the next updates continue exactly (counter-based
+ * noise). */
+mppi_status mppi_server_snapshot(mppi_server *srv, void *host_buf, size_t *size);
+mppi_status mppi_server_restore(mppi_server *srv, const void *host_buf, size_t size);
+
 /* --- profiling ---------------------------------------------------------------- */
 
 /* Per-kernel device time of mppi_update, and of mppi_batch_update's rollout stage and

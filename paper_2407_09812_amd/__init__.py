@@ -79,6 +79,33 @@ class BatchConfig(C.Structure):
                 ("blocks_per_cu", C.c_int32), ("use_graph", C.c_int32)]
 
 
+class ServerCfg(C.Structure):
+    _fields_ = [("device", C.c_int32), ("n_vehicles", C.c_int32), ("K_max", C.c_int32),
+                ("N_max", C.c_int32), ("M_max", C.c_int32), ("n_streams", C.c_int32),
+                ("max_batch", C.c_int32), ("reserved", C.c_int32), ("budget_bytes", C.c_int64),
+                ("veh", Vehicle), ("cost", Cost), ("u_init", C.c_float * 4)]
+
+
+class ServerRequest(C.Structure):
+    _fields_ = [("vehicle_id", C.c_uint32), ("K", C.c_int32), ("N", C.c_int32), ("M", C.c_int32),
+                ("dt", C.c_float), ("lam", C.c_float), ("sigma", C.c_float * 4),
+                ("seed", C.c_uint64), ("x_hat", C.c_void_p), ("x_ref", C.c_void_p),
+                ("obs", C.c_void_p)]
+
+
+class ServerResult(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("vehicle_id", C.c_uint32), ("t", C.c_uint32),
+                ("u_apply", C.c_float * 8), ("diag", Diag), ("submit_s", C.c_double),
+                ("launch_s", C.c_double), ("done_s", C.c_double), ("K", C.c_int32),
+                ("N", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("batches", C.c_int64),
+                ("rejected", C.c_int64), ("rollout_steps", C.c_int64),
+                ("max_in_flight", C.c_int64), ("busy_s", C.c_double)]
+
+
 class Profile(C.Structure):
     _fields_ = [("updates", C.c_int64), ("rollout_ms", C.c_double), ("weights_ms", C.c_double),
                 ("reduce_ms", C.c_double), ("apply_ms", C.c_double), ("batches", C.c_int64),
@@ -119,6 +146,16 @@ _SIGS = {
     "mppi_batch_autotune": [_vp, _vp, C.POINTER(Request), _i32, _i32, C.POINTER(BatchConfig)],
     "mppi_batch_get_config": [_vp, C.POINTER(BatchConfig)],
     "mppi_batch_set_config": [_vp, C.POINTER(BatchConfig)],
+    "mppi_server_create": [C.POINTER(ServerCfg), C.POINTER(_vp)],
+    "mppi_server_destroy": [_vp],
+    "mppi_server_set_batch_config": [_vp, C.POINTER(BatchConfig)],
+    "mppi_server_submit": [_vp, C.POINTER(ServerRequest), C.POINTER(C.c_uint64)],
+    "mppi_server_poll": [_vp, C.c_uint64, C.POINTER(ServerResult)],
+    "mppi_server_wait": [_vp, C.c_uint64, C.POINTER(ServerResult)],
+    "mppi_server_drain": [_vp],
+    "mppi_server_stats_get": [_vp, C.POINTER(ServerStats)],
+    "mppi_server_snapshot": [_vp, _vp, C.POINTER(C.c_size_t)],
+    "mppi_server_restore": [_vp, _vp, C.c_size_t],
     "mppi_profile_enable": [_vp, _i32],
     "mppi_profile_read": [_vp, C.POINTER(Profile)],
 }
@@ -130,11 +167,13 @@ _lib.mppi_status_str.argtypes = [C.c_int32]
 _lib.mppi_status_str.restype = C.c_char_p
 _lib.mppi_last_error.argtypes = [_vp]
 _lib.mppi_last_error.restype = C.c_char_p
+_lib.mppi_server_clock.argtypes = [_vp]
+_lib.mppi_server_clock.restype = C.c_double
 
 
 def exported_symbols():
     """Names of the C ABI entry points this binding resolves."""
-    return sorted(list(_SIGS) + ["mppi_status_str", "mppi_last_error"])
+    return sorted(list(_SIGS) + ["mppi_status_str", "mppi_last_error", "mppi_server_clock"])
 
 
 # --- marshalling ----------------------------------------------------------------
@@ -386,3 +425,115 @@ def mppi_profile_read(ctx) -> dict:
 
 def mppi_status_str(st: int) -> str:
     return _lib.mppi_status_str(int(st)).decode()
+
+
+# --- serving --------------------------------------------------------------------
+
+def _result_dict(r: ServerResult) -> dict:
+    return dict(ticket=r.ticket, vehicle_id=r.vehicle_id, t=r.t, u_apply=np.array(r.u_apply[:]),
+                status=r.diag.status, rho=r.diag.rho, ess=r.diag.ess, argmin=r.diag.argmin,
+                submit_s=r.submit_s, launch_s=r.launch_s, done_s=r.done_s, K=r.K, N=r.N,
+                latency_s=r.done_s - r.submit_s)
+
+
+class Server:
+    """mppi_server: continuous batching of MPPI updates for many vehicles."""
+
+    def __init__(self, veh, cst, u_init, n_vehicles, K_max, N_max, M_max, n_streams=2,
+                 max_batch=256, budget_bytes=2 << 30, device=0):
+        c = ServerCfg()
+        c.device, c.n_vehicles, c.K_max, c.N_max, c.M_max = device, n_vehicles, K_max, N_max, M_max
+        c.n_streams, c.max_batch, c.budget_bytes = n_streams, max_batch, int(budget_bytes)
+        c.veh, c.cost = vehicle(veh), cost(cst)
+        c.u_init = (C.c_float * 4)(*[float(v) for v in u_init])
+        h = C.c_void_p()
+        st = _lib.mppi_server_create(C.byref(c), C.byref(h))
+        if st != MPPI_OK:
+            raise MPPIError(st, "mppi_server_create")
+        self.handle = h
+
+    def _check(self, st, where):
+        if st != MPPI_OK:
+            raise MPPIError(st, where)
+
+    def set_batch_config(self, block, lanes, unroll, blocks_per_cu, use_graph=True):
+        c = BatchConfig(int(block), int(lanes), int(unroll), int(blocks_per_cu), 1 if use_graph else 0)
+        self._check(_lib.mppi_server_set_batch_config(self.handle, C.byref(c)),
+                    "mppi_server_set_batch_config")
+
+    def submit(self, vehicle_id, K, N, dt, lam, sigma, seed, x_hat, x_ref, obs=None) -> int:
+        """x_hat [17], x_ref [(N+1), 13] host arrays; obs an OBSTACLE_DTYPE array."""
+        r = ServerRequest()
+        r.vehicle_id, r.K, r.N = int(vehicle_id), int(K), int(N)
+        r.dt, r.lam = float(dt), float(lam)
+        r.sigma = (C.c_float * 4)(*[float(v) for v in sigma])
+        r.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+        xh = np.ascontiguousarray(x_hat, dtype=np.float32)
+        xr = np.ascontiguousarray(x_ref, dtype=np.float32)
+        if xh.size != 17 or xr.size != 13 * (int(N) + 1):
+            raise ValueError("x_hat must hold 17 values and x_ref (N+1) x 13")
+        r.x_hat, r.x_ref = xh.ctypes.data, xr.ctypes.data
+        if obs is not None and len(obs) > 0:
+            ob = np.ascontiguousarray(obs, dtype=OBSTACLE_DTYPE)
+            r.M, r.obs = ob.shape[0], ob.ctypes.data
+        else:
+            r.M, r.obs = 0, None
+        t = C.c_uint64()
+        self._check(_lib.mppi_server_submit(self.handle, C.byref(r), C.byref(t)), "mppi_server_submit")
+        return t.value
+
+    def poll(self, ticket):
+        r = ServerResult()
+        st = _lib.mppi_server_poll(self.handle, int(ticket), C.byref(r))
+        if st == -7:
+            return None
+        self._check(st, "mppi_server_poll")
+        return _result_dict(r)
+
+    def wait(self, ticket) -> dict:
+        r = ServerResult()
+        self._check(_lib.mppi_server_wait(self.handle, int(ticket), C.byref(r)), "mppi_server_wait")
+        return _result_dict(r)
+
+    def drain(self):
+        self._check(_lib.mppi_server_drain(self.handle), "mppi_server_drain")
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        self._check(_lib.mppi_server_stats_get(self.handle, C.byref(s)), "mppi_server_stats_get")
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def clock(self) -> float:
+        return _lib.mppi_server_clock(self.handle)
+
+    def snapshot(self) -> bytes:
+        n = C.c_size_t(0)
+        self._check(_lib.mppi_server_snapshot(self.handle, None, C.byref(n)), "mppi_server_snapshot")
+        buf = C.create_string_buffer(n.value)
+        self._check(_lib.mppi_server_snapshot(self.handle, buf, C.byref(n)), "mppi_server_snapshot")
+        return buf.raw
+
+    def restore(self, data: bytes):
+        buf = C.create_string_buffer(data, len(data))
+        self._check(_lib.mppi_server_restore(self.handle, buf, len(data)), "mppi_server_restore")
+
+    def close(self):
+        if self.handle:
+            _lib.mppi_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def obstacles_host(obs) -> np.ndarray:
+    """[M, 5] rows (type, cx, cy, cz, r) -> host array of mppi_obstacle structs."""
+    obs = np.asarray(obs, dtype=np.float64).reshape(-1, 5)
+    rec = np.zeros(obs.shape[0], dtype=OBSTACLE_DTYPE)
+    rec["type"] = obs[:, 0].astype(np.int32)
+    rec["c"] = obs[:, 1:4].astype(np.float32)
+    rec["r"] = obs[:, 4].astype(np.float32)
+    return rec

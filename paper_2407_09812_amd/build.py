@@ -10,7 +10,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "batch.hip", "api.hip", "batch_api.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "batch.hip", "api.hip", "batch_api.hip",
+                                           "server.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("kernels.h", "model.h", "stages.h", "batch.h",
                                            "context.h")] + [
     os.path.join(ROOT, "include", "mppi.h")]
@@ -26,7 +27,7 @@ def hipcc_flags():
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", *hipcc_flags(), "-shared", "-o", tmp, *SOURCES]
+    cmd = ["hipcc", *hipcc_flags(), "-shared", "-pthread", "-o", tmp, *SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

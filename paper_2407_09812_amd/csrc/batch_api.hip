@@ -179,14 +179,15 @@ void free_batch(mppi_ctx* ctx)
 
 }  // namespace mppi
 
-extern "C" {
+namespace mppi {
 
-mppi_status mppi_batch_reserve(mppi_ctx* ctx, const mppi_request* reqs, int32_t n)
+// Grow the batch arena to at least these capacities (instances, delta_u floats,
+// padded samples, control floats, smallest-tile work items, obstacles).
+mppi_status batch_reserve_raw(mppi_ctx* ctx, int n, size_t du, size_t k, size_t u, size_t items,
+                              int M)
 {
-    if (!ctx) return MPPI_E_INVALID_ARG;
     Needs nd;
-    mppi_status st = check_requests(ctx, reqs, n, &nd);
-    if (st != MPPI_OK) return st;
+    nd.n = n; nd.du = du; nd.k = k; nd.u = u; nd.items_min_tile = items; nd.M_max = M;
     BatchState& b = ctx->batch;
     if (b.plan_dev && capacity_ok(ctx, nd) == MPPI_OK) return MPPI_OK;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -217,6 +218,19 @@ mppi_status mppi_batch_reserve(mppi_ctx* ctx, const mppi_request* reqs, int32_t 
     b.n_cap = grow.n; b.M_cap = grow.M_max; b.du_cap = grow.du; b.k_cap = grow.k; b.u_cap = grow.u;
     b.items_cap = grow.items_min_tile; b.plan_bytes = L.bytes;
     return MPPI_OK;
+}
+
+}  // namespace mppi
+
+extern "C" {
+
+mppi_status mppi_batch_reserve(mppi_ctx* ctx, const mppi_request* reqs, int32_t n)
+{
+    if (!ctx) return MPPI_E_INVALID_ARG;
+    Needs nd;
+    mppi_status st = check_requests(ctx, reqs, n, &nd);
+    if (st != MPPI_OK) return st;
+    return batch_reserve_raw(ctx, nd.n, nd.du, nd.k, nd.u, nd.items_min_tile, nd.M_max);
 }
 
 mppi_status mppi_batch_update(mppi_ctx* ctx, void* stream, const mppi_request* reqs, int32_t n)

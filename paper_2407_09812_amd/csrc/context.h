@@ -67,6 +67,8 @@ ModelParams model_params(const mppi_vehicle& v, float dt);
 CostParams cost_params(const mppi_cost& c);
 NoiseParams noise_params(const mppi_solve& s);
 void free_batch(mppi_ctx* ctx);
+mppi_status batch_reserve_raw(mppi_ctx* ctx, int n, size_t du, size_t k, size_t u, size_t items,
+                              int M);
 hipEvent_t take_event(mppi_ctx* ctx);
 
 }  // namespace mppi

@@ -18,7 +18,7 @@ HEADER = os.path.join(ROOT, "include", "mppi.h")
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:mppi_status|const char \*)\s*(mppi_\w+)\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:mppi_status|const char \*|double)\s*(mppi_\w+)\(", text, re.M)))
 
 
 def test_header_declares_the_api():
@@ -60,7 +60,9 @@ def test_struct_layouts_match_the_c_header(tmp_path):
     structs = {"mppi_vehicle": lib.Vehicle, "mppi_cost": lib.Cost, "mppi_solve": lib.Solve,
                "mppi_diag": lib.Diag, "mppi_launch_config": lib.LaunchConfig,
                "mppi_request": lib.Request, "mppi_batch_config": lib.BatchConfig,
-               "mppi_profile": lib.Profile}
+               "mppi_profile": lib.Profile, "mppi_server_cfg": lib.ServerCfg,
+               "mppi_server_request": lib.ServerRequest, "mppi_server_result": lib.ServerResult,
+               "mppi_server_stats": lib.ServerStats}
     c_name = {"lam": "lambda"}            # ctypes cannot name a field after a Python keyword
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mppi.h"', "int main(void) {"]
     for cname, ct in structs.items():
@@ -80,6 +82,24 @@ def test_struct_layouts_match_the_c_header(tmp_path):
         for f, _ in ct._fields_:
             assert int(got[f"{cname}.{f}"]) == getattr(ct, f).offset, (cname, f)
     assert int(got["mppi_obstacle"]) == lib.OBSTACLE_DTYPE.itemsize
+
+
+def test_server_rejects_bad_configuration_on_the_host():
+    import paper_2407_09812_amd as lib
+    import workloads as W
+    veh, cost = W.vehicle_benchmark(), W.cost_benchmark()
+    for kw in (dict(n_vehicles=0), dict(N_max=5000), dict(n_streams=0), dict(max_batch=0),
+               dict(budget_bytes=0), dict(M_max=-1)):
+        args = dict(n_vehicles=4, K_max=256, N_max=50, M_max=10, n_streams=2, max_batch=8,
+                    budget_bytes=1 << 24)
+        args.update(kw)
+        with pytest.raises(lib.MPPIError) as e:
+            lib.Server(veh, cost, W.hover_control(veh), **args)
+        assert e.value.status == -1
+    with pytest.raises(lib.MPPIError) as e:
+        lib.Server(dict(veh, mass=-1.0), cost, W.hover_control(veh), n_vehicles=4, K_max=256,
+                   N_max=50, M_max=10)
+    assert e.value.status == -1
 
 
 def _good():

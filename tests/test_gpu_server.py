@@ -1,0 +1,166 @@
+"""Serving: continuous batching of MPPI updates for many vehicles.
+
+Bars: every served result (applied control, diagnostics, final warm starts) is bit-
+identical to the same vehicle's updates run alone, in order, with mppi_update;
+requests are coalesced into batches and two slots run at once; a snapshot restores
+the exact continuation; budget and argument errors are reported.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from gpu_support import dev
+
+pytestmark = pytest.mark.gpu
+
+K_CHOICES = (64, 200, 1024, 2048)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2407_09812_amd as lib
+    return lib
+
+
+def make_requests(n_req, n_veh, seed, N_max=64, M_max=40):
+    rng = np.random.default_rng(seed)
+    fleet = [W.random_vehicle(rng, v, seed, K=64, N=N_max, M=int(rng.integers(0, M_max + 1)))
+             for v in range(n_veh)]
+    reqs, count = [], [0] * n_veh
+    for _ in range(n_req):
+        v = int(rng.integers(0, n_veh))
+        sc = fleet[v]
+        K, N = int(rng.choice(K_CHOICES)), int(rng.integers(5, N_max + 1))
+        t = count[v]
+        count[v] += 1
+        x_hat = W.state_on_reference(sc.ref, t * sc.dt, sc.veh)
+        x_hat[:3] += rng.normal(0, 0.05, 3)
+        reqs.append(dict(vid=v, K=K, N=N, dt=sc.dt, lam=sc.lam, sigma=sc.sigma, seed=seed,
+                         x_hat=x_hat.astype(np.float32),
+                         x_ref=sc.ref.rows(t * sc.dt, N, sc.dt).astype(np.float32),
+                         obs=sc.obstacles))
+    return fleet, reqs
+
+
+def new_server(lib, n_veh, n_streams=2, max_batch=4, budget=64 << 20, N_max=64):
+    veh, cost = W.vehicle_benchmark(), W.cost_benchmark()
+    srv = lib.Server(veh, cost, W.hover_control(veh), n_vehicles=n_veh, K_max=2048, N_max=N_max,
+                     M_max=40, n_streams=n_streams, max_batch=max_batch, budget_bytes=budget)
+    srv.set_batch_config(256, 1, 4, 4)
+    return srv
+
+
+def submit_all(lib, srv, reqs):
+    return [srv.submit(r["vid"], r["K"], r["N"], r["dt"], r["lam"], r["sigma"], r["seed"],
+                       r["x_hat"], r["x_ref"], lib.obstacles_host(r["obs"])) for r in reqs]
+
+
+def replay_alone(lib, reqs, results, n_veh, N_max=64, warm=None, t0=None):
+    """Each vehicle's requests in order through mppi_update from its own warm start."""
+    veh, cost = W.vehicle_benchmark(), W.cost_benchmark()
+    u_init = W.hover_control(veh)
+    ctx = lib.Context(0)
+    lib.mppi_reserve(ctx, 2048, N_max, 40)
+    u_full = [dev(np.tile(u_init, (N_max, 1))) if warm is None else dev(warm[v]) for v in range(n_veh)]
+    outs = []
+    for r, res in zip(reqs, results):
+        v, K, N = r["vid"], r["K"], r["N"]
+        M = r["obs"].shape[0]
+        lib.mppi_set_config(ctx, K, N, M, 64, 1, 1)
+        solve = dict(K=K, N=N, dt=r["dt"], lam=r["lam"], sigma=r["sigma"], u_init=u_init,
+                     seed=r["seed"], vehicle_id=v, t=res["t"])
+        u_apply = torch.empty(8, device="cuda")
+        diag = lib.new_diag()
+        lib.mppi_update(ctx, veh, cost, solve, dev(r["x_hat"]), dev(r["x_ref"]),
+                        lib.obstacles_to_device(r["obs"]), M, u_full[v][:N], u_apply, diag)
+        torch.cuda.synchronize()
+        outs.append((u_apply.cpu().numpy(), lib.diag_from_tensor(diag)))
+    warm_out = np.stack([u.cpu().numpy() for u in u_full])
+    ctx.close()
+    return outs, warm_out
+
+
+def test_served_equals_alone_bitwise(lib):
+    n_veh = 6
+    fleet, reqs = make_requests(40, n_veh, seed=61)
+    srv = new_server(lib, n_veh)
+    try:
+        tickets = submit_all(lib, srv, reqs)
+        results = [srv.wait(t) for t in tickets]
+        stats = srv.stats()
+        snap = np.frombuffer(srv.snapshot(), dtype=np.uint8)
+    finally:
+        srv.close()
+    print("server stats", stats)
+    assert stats["completed"] == 40 and stats["batches"] < 40          # coalesced
+    assert all(r["status"] == 0 for r in results)
+    per_vehicle_t = {}
+    for r, res in zip(reqs, results):                                    # per-vehicle order
+        assert res["t"] == per_vehicle_t.get(r["vid"], 0)
+        per_vehicle_t[r["vid"]] = res["t"] + 1
+    alone, warm = replay_alone(lib, reqs, results, n_veh)
+    for res, (ua, dg) in zip(results, alone):
+        assert np.array_equal(res["u_apply"].astype(np.float32), ua)
+        assert res["rho"] == dg["rho"] and res["argmin"] == dg["argmin"] and res["ess"] == dg["ess"]
+    warm_srv = snap[: warm.nbytes].view(np.float32).reshape(warm.shape)
+    assert np.array_equal(warm_srv, warm)
+
+
+def test_two_slots_overlap_and_batches_coalesce(lib):
+    n_veh = 16
+    _, reqs = make_requests(64, n_veh, seed=62)
+    srv = new_server(lib, n_veh, n_streams=2, max_batch=4)
+    try:
+        tickets = submit_all(lib, srv, reqs)
+        srv.drain()
+        stats = srv.stats()
+        lat = [srv.poll(t)["latency_s"] for t in tickets]
+    finally:
+        srv.close()
+    print("stats", stats, "p50 latency ms", 1e3 * np.median(lat))
+    assert stats["completed"] == 64 and stats["batches"] <= 64
+    assert stats["max_in_flight"] > 4          # more than one slot's batch in flight at once
+    assert all(np.isfinite(lat)) and min(lat) > 0
+
+
+def test_snapshot_restore_continues_exactly(lib):
+    n_veh = 4
+    _, reqs = make_requests(24, n_veh, seed=63)
+    first, second = reqs[:12], reqs[12:]
+    a = new_server(lib, n_veh)
+    try:
+        [a.wait(t) for t in submit_all(lib, a, first)]
+        snap = a.snapshot()
+        res_a = [a.wait(t) for t in submit_all(lib, a, second)]
+    finally:
+        a.close()
+    b = new_server(lib, n_veh, n_streams=1, max_batch=3)
+    try:
+        b.restore(snap)
+        res_b = [b.wait(t) for t in submit_all(lib, b, second)]
+    finally:
+        b.close()
+    for x, y in zip(res_a, res_b):
+        assert x["t"] == y["t"] and np.array_equal(x["u_apply"], y["u_apply"])
+
+
+def test_budget_and_argument_errors(lib):
+    srv = new_server(lib, 3, n_streams=1, budget=1 << 20)        # 1 MiB of delta_u per slot
+    try:
+        _, reqs = make_requests(1, 3, seed=64)
+        r = dict(reqs[0], K=2048, N=64, x_ref=np.zeros((65, 13), np.float32))
+        with pytest.raises(lib.MPPIError) as e:                  # 2048 x 64 x 16 B > 1 MiB
+            submit_all(lib, srv, [r])
+        assert e.value.status == -4
+        with pytest.raises(lib.MPPIError) as e:
+            submit_all(lib, srv, [dict(reqs[0], vid=7)])
+        assert e.value.status == -1
+        with pytest.raises(ValueError):
+            submit_all(lib, srv, [dict(reqs[0], x_ref=np.zeros((3, 13), np.float32))])
+        with pytest.raises(lib.MPPIError) as e:                  # never issued
+            srv.poll(12345)
+        assert e.value.status == -1
+        assert srv.stats()["rejected"] == 1
+    finally:
+        srv.close()

@@ -62,59 +62,54 @@ def hover_control(veh: dict) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# Rotations used to build references (not part of the method)
+# Rotations used to build references (not part of the method), vectorised
 # ---------------------------------------------------------------------------
 
-def _quat_from_matrix(Rm: np.ndarray) -> np.ndarray:
-    tr = Rm[0, 0] + Rm[1, 1] + Rm[2, 2]
-    if tr > 0.0:
-        s = math.sqrt(tr + 1.0) * 2.0
-        q = [0.25 * s, (Rm[2, 1] - Rm[1, 2]) / s, (Rm[0, 2] - Rm[2, 0]) / s, (Rm[1, 0] - Rm[0, 1]) / s]
-    elif Rm[0, 0] > Rm[1, 1] and Rm[0, 0] > Rm[2, 2]:
-        s = math.sqrt(1.0 + Rm[0, 0] - Rm[1, 1] - Rm[2, 2]) * 2.0
-        q = [(Rm[2, 1] - Rm[1, 2]) / s, 0.25 * s, (Rm[0, 1] + Rm[1, 0]) / s, (Rm[0, 2] + Rm[2, 0]) / s]
-    elif Rm[1, 1] > Rm[2, 2]:
-        s = math.sqrt(1.0 + Rm[1, 1] - Rm[0, 0] - Rm[2, 2]) * 2.0
-        q = [(Rm[0, 2] - Rm[2, 0]) / s, (Rm[0, 1] + Rm[1, 0]) / s, 0.25 * s, (Rm[1, 2] + Rm[2, 1]) / s]
-    else:
-        s = math.sqrt(1.0 + Rm[2, 2] - Rm[0, 0] - Rm[1, 1]) * 2.0
-        q = [(Rm[1, 0] - Rm[0, 1]) / s, (Rm[0, 2] + Rm[2, 0]) / s, (Rm[1, 2] + Rm[2, 1]) / s, 0.25 * s]
-    q = np.array(q)
-    q /= np.linalg.norm(q)
-    return q if q[0] >= 0.0 else -q
+def _quats_from_frames(xb, yb, zb):
+    """Unit quaternions [n, 4] (w first, w >= 0) of the rotation matrices whose
+    columns are xb, yb, zb [n, 3] (Shepperd's method, best-conditioned branch)."""
+    R = np.stack([xb, yb, zb], axis=2)                 # R[:, i, j] = column j, row i
+    r00, r11, r22 = R[:, 0, 0], R[:, 1, 1], R[:, 2, 2]
+    t = np.stack([1 + r00 + r11 + r22, 1 + r00 - r11 - r22,
+                  1 - r00 + r11 - r22, 1 - r00 - r11 + r22], axis=1)
+    k = np.argmax(t, axis=1)
+    s = 2.0 * np.sqrt(np.maximum(t[np.arange(len(k)), k], 1e-300))
+    q = np.empty((len(k), 4))
+    d21, d02, d10 = R[:, 2, 1] - R[:, 1, 2], R[:, 0, 2] - R[:, 2, 0], R[:, 1, 0] - R[:, 0, 1]
+    s01, s02, s12 = R[:, 0, 1] + R[:, 1, 0], R[:, 0, 2] + R[:, 2, 0], R[:, 1, 2] + R[:, 2, 1]
+    cases = [np.stack([0.25 * s, d21 / s, d02 / s, d10 / s], 1),
+             np.stack([d21 / s, 0.25 * s, s01 / s, s02 / s], 1),
+             np.stack([d02 / s, s01 / s, 0.25 * s, s12 / s], 1),
+             np.stack([d10 / s, s02 / s, s12 / s, 0.25 * s], 1)]
+    for c in range(4):
+        q[k == c] = cases[c][k == c]
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    return np.where(q[:, :1] < 0.0, -q, q)
 
 
-def _attitude_from_acceleration(acc: np.ndarray, yaw: float = 0.0) -> np.ndarray:
-    """Differential flatness: body z along acc + g e_z, heading `yaw`."""
+def _attitudes(acc: np.ndarray, yaw: float = 0.0) -> np.ndarray:
+    """Differential flatness: body z along acc + g e_z, heading `yaw` ([n, 3] -> [n, 4])."""
     zb = acc + np.array([0.0, 0.0, G])
-    zb = zb / np.linalg.norm(zb)
+    zb = zb / np.linalg.norm(zb, axis=1, keepdims=True)
     xc = np.array([math.cos(yaw), math.sin(yaw), 0.0])
     yb = np.cross(zb, xc)
-    yb /= np.linalg.norm(yb)
+    yb /= np.linalg.norm(yb, axis=1, keepdims=True)
     xb = np.cross(yb, zb)
-    return _quat_from_matrix(np.column_stack([xb, yb, zb]))
+    return _quats_from_frames(xb, yb, zb)
 
 
-def _quat_conj(q):
-    return np.array([q[0], -q[1], -q[2], -q[3]])
-
-
-def _quat_mul(a, b):
-    return np.array([
-        a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3],
-        a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2],
-        a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1],
-        a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0]])
-
-
-def _body_rate(q_prev, q_next, h):
-    """Body rate carrying q_prev to q_next over time h (finite difference)."""
-    dq = _quat_mul(_quat_conj(q_prev), q_next)
-    if dq[0] < 0.0:
-        dq = -dq
-    ang = 2.0 * math.atan2(np.linalg.norm(dq[1:]), dq[0])
-    n = np.linalg.norm(dq[1:])
-    return np.zeros(3) if n < 1e-15 else dq[1:] / n * ang / h
+def _body_rates(q_prev, q_next, h):
+    """Body rates [n, 3] carrying q_prev to q_next over time h (finite difference)."""
+    w1, v1 = q_prev[:, 0], -q_prev[:, 1:]
+    w2, v2 = q_next[:, 0], q_next[:, 1:]
+    dw = w1 * w2 - np.sum(v1 * v2, axis=1)
+    dv = w1[:, None] * v2 + w2[:, None] * v1 + np.cross(v1, v2)
+    sign = np.where(dw < 0.0, -1.0, 1.0)
+    dw, dv = dw * sign, dv * sign[:, None]
+    n = np.linalg.norm(dv, axis=1)
+    ang = 2.0 * np.arctan2(n, dw)
+    scale = np.where(n < 1e-15, 0.0, ang / np.maximum(n, 1e-300) / h)
+    return dv * scale[:, None]
 
 
 # ---------------------------------------------------------------------------
@@ -122,29 +117,33 @@ def _body_rate(q_prev, q_next, h):
 # ---------------------------------------------------------------------------
 
 class Reference:
-    """Base class: position/velocity/acceleration as functions of time."""
+    """Position, velocity and acceleration as functions of time (vectorised over
+    an array of times); attitude by differential flatness with zero yaw, body rates
+    by central differences of the attitude."""
 
-    def pva(self, tau: float):
+    def pva(self, tau: np.ndarray):
         raise NotImplementedError
 
     def yaw(self) -> float:
         return 0.0
 
-    def row(self, tau: float, h: float = 1e-3) -> np.ndarray:
-        p, v, a = self.pva(tau)
-        q = _attitude_from_acceleration(a, self.yaw())
-        _, _, a_prev = self.pva(tau - h)
-        _, _, a_next = self.pva(tau + h)
-        q_prev = _attitude_from_acceleration(a_prev, self.yaw())
-        q_next = _attitude_from_acceleration(a_next, self.yaw())
-        w = _body_rate(q_prev, q_next, 2.0 * h)
-        return np.concatenate([p, q, v, w])
+    def rows_at(self, taus, h: float = 1e-3) -> np.ndarray:
+        taus = np.asarray(taus, dtype=np.float64)
+        p, v, a = self.pva(taus)
+        q = _attitudes(a, self.yaw())
+        q_prev = _attitudes(self.pva(taus - h)[2], self.yaw())
+        q_next = _attitudes(self.pva(taus + h)[2], self.yaw())
+        w = _body_rates(q_prev, q_next, 2.0 * h)
+        return np.concatenate([p, q, v, w], axis=1)
+
+    def row(self, tau: float) -> np.ndarray:
+        return self.rows_at([tau])[0]
 
     def rows(self, t0: float, N: int, dt: float) -> np.ndarray:
-        return np.stack([self.row(t0 + j * dt) for j in range(N + 1)])
+        return self.rows_at(t0 + dt * np.arange(N + 1))
 
     def thrust(self, tau: float, mass: float) -> float:
-        _, _, a = self.pva(tau)
+        a = self.pva(np.array([tau]))[2][0]
         return mass * float(np.linalg.norm(a + np.array([0.0, 0.0, G])))
 
 
@@ -153,7 +152,8 @@ class PointReference(Reference):
         self.point = np.asarray(point, dtype=np.float64)
 
     def pva(self, tau):
-        return self.point.copy(), np.zeros(3), np.zeros(3)
+        n = np.size(tau)
+        return np.tile(self.point, (n, 1)), np.zeros((n, 3)), np.zeros((n, 3))
 
 
 class LineReference(Reference):
@@ -162,7 +162,9 @@ class LineReference(Reference):
         self.vel = np.asarray(velocity, dtype=np.float64)
 
     def pva(self, tau):
-        return self.start + self.vel * tau, self.vel.copy(), np.zeros(3)
+        tau = np.atleast_1d(tau)[:, None]
+        return self.start + self.vel * tau, np.tile(self.vel, (tau.shape[0], 1)), \
+            np.zeros((tau.shape[0], 3))
 
 
 class CircleReference(Reference):
@@ -173,11 +175,11 @@ class CircleReference(Reference):
         self.phase = float(phase)
 
     def pva(self, tau):
-        a = self.phase + self.om * tau
-        ca, sa = math.cos(a), math.sin(a)
-        p = self.c + self.r * np.array([ca, sa, 0.0])
-        v = self.r * self.om * np.array([-sa, ca, 0.0])
-        acc = -self.r * self.om ** 2 * np.array([ca, sa, 0.0])
+        a = self.phase + self.om * np.atleast_1d(tau)
+        ca, sa, z = np.cos(a), np.sin(a), np.zeros_like(a)
+        p = self.c + self.r * np.stack([ca, sa, z], 1)
+        v = self.r * self.om * np.stack([-sa, ca, z], 1)
+        acc = -self.r * self.om ** 2 * np.stack([ca, sa, z], 1)
         return p, v, acc
 
 
