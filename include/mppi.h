@@ -121,7 +121,8 @@ typedef struct mppi_diag {
     int32_t argmin;    /* smallest k with S_k = rho                       */
     int32_t n_finite;  /* number of finite costs                          */
     int32_t status;    /* MPPI_OK or MPPI_E_ALL_NONFINITE                 */
-    float reserved[2];
+    int32_t lanes;     /* lanes per sample the rollouts ran with          */
+    float reserved;
 } mppi_diag;
 
 typedef struct mppi_ctx mppi_ctx;
@@ -250,9 +251,11 @@ typedef struct mppi_request {
 } mppi_request;
 
 /* Launch shape of the batched rollout: workgroup size (64, 128, 256), lanes per
- * sample (1, 2, 4, 8; must divide block), obstacle-loop unroll (1, 4), persistent
- * workgroups per compute unit (1..16), and whether to replay a captured HIP graph
- * (1) or launch the kernels one by one (0). */
+ * sample (1, 2, 4, 8 for every instance, or 0 = per instance: as many as keep the
+ * whole batch near one wave per SIMD, capped by the instance's obstacle count),
+ * obstacle-loop unroll (1, 4), persistent workgroups per compute unit (1..16), and
+ * whether to replay a captured HIP graph (1) or launch the kernels one by one (0).
+ * Each instance reports the lanes it ran with in its mppi_diag. */
 typedef struct mppi_batch_config {
     int32_t block;
     int32_t lanes;
@@ -268,7 +271,7 @@ mppi_status mppi_batch_reserve(mppi_ctx *ctx, const mppi_request *reqs, int32_t 
 
 /* MPPI updates of n independent instances with uneven K, N and M in one launch
  * sequence on `stream` (Algorithm 1 loop body for each; the same results, bit for
- * bit, as mppi_update with the same lanes per sample).  A persistent rollout kernel
+ * bit, as mppi_update with the same lanes per sample, see mppi_diag.lanes).  A persistent rollout kernel
  * takes (instance, sample tile) items longest first from a device queue; weights,
  * weighted sums and shifts follow per instance.  With use_graph the sequence is a HIP
  * graph captured once per launch shape and replayed.  Host-side planning is copied

@@ -61,7 +61,7 @@ class Solve(C.Structure):
 class Diag(C.Structure):
     _fields_ = [("rho", C.c_float), ("eta", C.c_float), ("ess", C.c_float),
                 ("argmin", C.c_int32), ("n_finite", C.c_int32), ("status", C.c_int32),
-                ("reserved", C.c_float * 2)]
+                ("lanes", C.c_int32), ("reserved", C.c_float)]
 
 
 class LaunchConfig(C.Structure):
@@ -237,7 +237,7 @@ def diag_from_tensor(t: torch.Tensor) -> dict:
     raw = t.detach().cpu().numpy().tobytes()
     d = Diag.from_buffer_copy(raw[:C.sizeof(Diag)])
     return dict(rho=d.rho, eta=d.eta, ess=d.ess, argmin=d.argmin, n_finite=d.n_finite,
-                status=d.status)
+                status=d.status, lanes=d.lanes)
 
 
 def new_diag(device="cuda") -> torch.Tensor:
@@ -432,6 +432,7 @@ def mppi_status_str(st: int) -> str:
 def _result_dict(r: ServerResult) -> dict:
     return dict(ticket=r.ticket, vehicle_id=r.vehicle_id, t=r.t, u_apply=np.array(r.u_apply[:]),
                 status=r.diag.status, rho=r.diag.rho, ess=r.diag.ess, argmin=r.diag.argmin,
+                lanes=r.diag.lanes,
                 submit_s=r.submit_s, launch_s=r.launch_s, done_s=r.done_s, K=r.K, N=r.N,
                 latency_s=r.done_s - r.submit_s)
 

@@ -316,10 +316,11 @@ mppi_status mppi_update(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh, co
         return ctx->profiling ? hipEventRecord(ev[i], s) : hipSuccess;
     };
 
+    const LaunchConfig cfg = config_for(ctx, solve->K, solve->N, M);
     HIP_TRY(ctx, mark(0));
-    HIP_TRY(ctx, launch_rollout(a, config_for(ctx, solve->K, solve->N, M), s));
+    HIP_TRY(ctx, launch_rollout(a, cfg, s));
     HIP_TRY(ctx, mark(1));
-    HIP_TRY(ctx, launch_weights(ctx->S, solve->K, solve->lambda, ctx->w, dg, s));
+    HIP_TRY(ctx, launch_weights(ctx->S, solve->K, solve->lambda, ctx->w, dg, cfg.lanes, s));
     HIP_TRY(ctx, mark(2));
     HIP_TRY(ctx, launch_weighted_sum(ctx->w, ctx->du, solve->K, solve->N, ctx->ld, u_nom,
                                      ctx->u_upd, dg, s));
@@ -421,7 +422,7 @@ mppi_status mppi_weights(mppi_ctx* ctx, void* stream, int32_t K, const float* S,
     if (!ctx) return MPPI_E_INVALID_ARG;
     if (K < 1 || !S || !w || !diag || !std::isfinite(lambda) || !(lambda > 0))
         return fail(ctx, MPPI_E_INVALID_ARG, "weights: bad argument");
-    HIP_TRY(ctx, launch_weights(S, K, lambda, w, diag, (hipStream_t)stream));
+    HIP_TRY(ctx, launch_weights(S, K, lambda, w, diag, 0, (hipStream_t)stream));
     return MPPI_OK;
 }
 

@@ -16,6 +16,7 @@ struct InstanceDesc {
     float lambda;
     float u_init[4];
     int row0;                    // first weighted-sum row of this instance (4 N rows)
+    int lanes;                   // lanes per sample (1, 2, 4, 8)
     const float* x_hat;
     const float* x_ref;
     const mppi_obstacle* obs;
@@ -43,7 +44,8 @@ struct BatchHeader {
 };
 
 // Launch shape of the batched rollout: `block` threads per workgroup, `lanes` per
-// sample, obstacle loop `unroll`, `blocks_per_cu` persistent workgroups per CU.
+// sample (0: chosen per instance at planning), obstacle loop `unroll`,
+// `blocks_per_cu` persistent workgroups per CU.
 struct BatchLaunch {
     int block, lanes, unroll, blocks_per_cu;
 };

@@ -24,6 +24,19 @@ __global__ void batch_reset_kernel(BatchHeader* hdr)
 }
 
 template <int L, int U>
+__device__ __forceinline__ void batch_tile(const InstanceDesc& D, int k0, const float4* obs_lds)
+{
+    const int k = k0 + (int)threadIdx.x / L, q = (int)threadIdx.x % L;
+    if (k >= D.rp.K) return;
+    if (D.rp.mp.lag)
+        rollout_sample<L, U, true, false>(D.rp, D.x_hat, D.x_ref, D.u_nom, D.du, D.S, nullptr,
+                                          obs_lds, k, q);
+    else
+        rollout_sample<L, U, false, false>(D.rp, D.x_hat, D.x_ref, D.u_nom, D.du, D.S, nullptr,
+                                           obs_lds, k, q);
+}
+
+template <int U>
 __global__ __launch_bounds__(256) void batch_rollout_kernel(BatchHeader* hdr,
                                                            const InstanceDesc* __restrict__ descs,
                                                            const WorkItem* __restrict__ items)
@@ -43,14 +56,11 @@ __global__ __launch_bounds__(256) void batch_rollout_kernel(BatchHeader* hdr,
         stage_obstacles(obs_lds, D.obs, D.rp.M, D.x_hat[0], D.x_hat[1], D.x_hat[2],
                         D.rp.cp.margin);
         __syncthreads();
-        const int k = k0 + (int)threadIdx.x / L, q = (int)threadIdx.x % L;
-        if (k < D.rp.K) {
-            if (D.rp.mp.lag)
-                rollout_sample<L, U, true, false>(D.rp, D.x_hat, D.x_ref, D.u_nom, D.du, D.S,
-                                                  nullptr, obs_lds, k, q);
-            else
-                rollout_sample<L, U, false, false>(D.rp, D.x_hat, D.x_ref, D.u_nom, D.du, D.S,
-                                                   nullptr, obs_lds, k, q);
+        switch (__builtin_amdgcn_readfirstlane(D.lanes)) {   // uniform per item
+        case 1: batch_tile<1, U>(D, k0, obs_lds); break;
+        case 2: batch_tile<2, U>(D, k0, obs_lds); break;
+        case 4: batch_tile<4, U>(D, k0, obs_lds); break;
+        default: batch_tile<8, U>(D, k0, obs_lds); break;
         }
         __syncthreads();                       // LDS is restaged for the next item
     }
@@ -62,7 +72,7 @@ __global__ __launch_bounds__(kWeightsThreads) void batch_weights_kernel(
     const int i = blockIdx.x;
     if (i >= hdr->n_inst) return;
     const InstanceDesc& D = descs[i];
-    weights_block(D.S, D.rp.K, D.lambda, D.w, D.diag);
+    weights_block(D.S, D.rp.K, D.lambda, D.w, D.diag, D.lanes);
 }
 
 __global__ __launch_bounds__(kSumThreads) void batch_wsum_kernel(const BatchHeader* __restrict__ hdr,
@@ -95,9 +105,8 @@ __global__ void batch_apply_kernel(const BatchHeader* __restrict__ hdr,
 bool valid_batch_launch(const BatchLaunch& c)
 {
     return (c.block == 64 || c.block == 128 || c.block == 256) &&
-           (c.lanes == 1 || c.lanes == 2 || c.lanes == 4 || c.lanes == 8) &&
-           (c.unroll == 1 || c.unroll == 4) && c.blocks_per_cu >= 1 && c.blocks_per_cu <= 16 &&
-           c.block % c.lanes == 0;
+           (c.lanes == 0 || c.lanes == 1 || c.lanes == 2 || c.lanes == 4 || c.lanes == 8) &&
+           (c.unroll == 1 || c.unroll == 4) && c.blocks_per_cu >= 1 && c.blocks_per_cu <= 16;
 }
 
 hipError_t launch_batch_rollout(BatchHeader* hdr, const InstanceDesc* descs, const WorkItem* items,
@@ -107,18 +116,12 @@ hipError_t launch_batch_rollout(BatchHeader* hdr, const InstanceDesc* descs, con
     if (!valid_batch_launch(c)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, stream, hdr);
     const dim3 grid(cu_count * c.blocks_per_cu), block(c.block);
-#define MPPI_BATCH_ROLLOUT(L, U) \
-    hipLaunchKernelGGL((batch_rollout_kernel<L, U>), grid, block, lds_bytes, stream, hdr, descs, items)
-    switch (c.lanes * 10 + c.unroll) {
-    case 11: MPPI_BATCH_ROLLOUT(1, 1); break;
-    case 14: MPPI_BATCH_ROLLOUT(1, 4); break;
-    case 21: MPPI_BATCH_ROLLOUT(2, 1); break;
-    case 24: MPPI_BATCH_ROLLOUT(2, 4); break;
-    case 41: MPPI_BATCH_ROLLOUT(4, 1); break;
-    case 44: MPPI_BATCH_ROLLOUT(4, 4); break;
-    case 81: MPPI_BATCH_ROLLOUT(8, 1); break;
-    default: MPPI_BATCH_ROLLOUT(8, 4); break;
-    }
+#define MPPI_BATCH_ROLLOUT(U) \
+    hipLaunchKernelGGL((batch_rollout_kernel<U>), grid, block, lds_bytes, stream, hdr, descs, items)
+    if (c.unroll == 4)
+        MPPI_BATCH_ROLLOUT(4);
+    else
+        MPPI_BATCH_ROLLOUT(1);
 #undef MPPI_BATCH_ROLLOUT
     return hipGetLastError();
 }

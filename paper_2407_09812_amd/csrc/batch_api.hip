@@ -82,7 +82,14 @@ size_t fill_plan(mppi_ctx* ctx, const mppi_request* reqs, int n, const BatchLaun
     InstanceDesc* descs = reinterpret_cast<InstanceDesc*>(host + L.descs_off);
     WorkItem* items = reinterpret_cast<WorkItem*>(host + L.items_off);
 
-    const int tile = cfg.block / cfg.lanes;
+    // lanes per instance: fixed, or (cfg.lanes == 0) as many as keep the whole batch
+    // near one wave per SIMD, capped so that each lane keeps >= 8 obstacles to test
+    int auto_lanes = 1;
+    if (cfg.lanes == 0) {
+        long long waves = 0;
+        for (int i = 0; i < n; ++i) waves += (reqs[i].solve.K + 63) / 64;
+        while (auto_lanes < 8 && waves * auto_lanes * 2 <= 1024) auto_lanes *= 2;
+    }
     size_t du_off = 0, k_off = 0, u_off = 0;
     int row = 0;
     struct Keyed { long long cost; int inst, k0; };
@@ -98,13 +105,20 @@ size_t fill_plan(mppi_ctx* ctx, const mppi_request* reqs, int n, const BatchLaun
         D.lambda = q.solve.lambda;
         for (int d = 0; d < 4; ++d) D.u_init[d] = q.solve.u_init[d];
         D.row0 = row;
+        int lanes = cfg.lanes;
+        if (lanes == 0) {
+            lanes = 1;
+            while (lanes < auto_lanes && q.M >= 8 * 2 * lanes) lanes *= 2;
+        }
+        D.lanes = lanes;
+        const int tile = cfg.block / lanes;
         D.x_hat = q.x_hat; D.x_ref = q.x_ref; D.obs = q.obs;
         D.u_nom = q.u_nom; D.u_apply = q.u_apply;
         D.diag = q.diag ? q.diag : b.diags + i;
         D.du = b.du + du_off; D.S = b.S + k_off; D.w = b.w + k_off; D.u_upd = b.u_upd + u_off;
         du_off += 4 * (size_t)N * ld; k_off += ld; u_off += 4 * (size_t)N; row += 4 * N;
         // cost of one tile: N steps of dynamics plus this lane's share of the obstacles
-        const long long cost = (long long)N * (650 + 11 * ((q.M + cfg.lanes - 1) / cfg.lanes));
+        const long long cost = (long long)N * (650 + 11 * ((q.M + lanes - 1) / lanes));
         for (int k0 = 0; k0 < K; k0 += tile) work.push_back({cost, i, k0});
     }
     std::stable_sort(work.begin(), work.end(),
@@ -317,7 +331,7 @@ mppi_status mppi_batch_autotune(mppi_ctx* ctx, void* stream, const mppi_request*
     HIP_TRY(ctx, hipEventCreate(&e0));
     HIP_TRY(ctx, hipEventCreate(&e1));
     std::vector<BatchLaunch> candidates;
-    for (int lanes : {1, 2, 4})
+    for (int lanes : {0, 1, 2, 4})
         for (int block : {64, 128, 256})
             for (int unroll : {1, 4})
                 for (int bpc : {1, 2, 4, 8}) {

@@ -38,7 +38,7 @@ struct LaunchConfig {
 
 bool valid_config(const LaunchConfig& c);
 hipError_t launch_rollout(const RolloutArgs& a, const LaunchConfig& cfg, hipStream_t stream);
-hipError_t launch_weights(const float* S, int K, float lambda, float* w, mppi_diag* diag,
+hipError_t launch_weights(const float* S, int K, float lambda, float* w, mppi_diag* diag, int lanes,
                           hipStream_t stream);
 hipError_t launch_weighted_sum(const float* w, const float* du, int K, int N, int ld,
                                const float* u_in, float* u_out, const mppi_diag* diag,

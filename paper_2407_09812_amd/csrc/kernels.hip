@@ -34,9 +34,9 @@ __global__ __launch_bounds__(256) void rollout_kernel(
 
 __global__ __launch_bounds__(kWeightsThreads) void weights_kernel(const float* __restrict__ S, int K,
                                                                  float lambda, float* __restrict__ w,
-                                                                 mppi_diag* __restrict__ diag)
+                                                                 mppi_diag* __restrict__ diag, int lanes)
 {
-    weights_block(S, K, lambda, w, diag);
+    weights_block(S, K, lambda, w, diag, lanes);
 }
 
 __global__ __launch_bounds__(kSumThreads) void weighted_sum_kernel(
@@ -143,11 +143,11 @@ hipError_t launch_rollout(const RolloutArgs& a, const LaunchConfig& c, hipStream
     }
 }
 
-hipError_t launch_weights(const float* S, int K, float lambda, float* w, mppi_diag* diag,
+hipError_t launch_weights(const float* S, int K, float lambda, float* w, mppi_diag* diag, int lanes,
                           hipStream_t stream)
 {
     hipLaunchKernelGGL(weights_kernel, dim3(1), dim3(kWeightsThreads), 0, stream, S, K, lambda, w,
-                       diag);
+                       diag, lanes);
     return hipGetLastError();
 }
 

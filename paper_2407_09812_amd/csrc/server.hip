@@ -104,7 +104,7 @@ struct mppi_server {
     int busy_slots = 0;
     double busy_since = 0.0;
     int64_t in_flight_reqs = 0;
-    mppi_batch_config bcfg{256, 1, 4, 8, 1};
+    mppi_batch_config bcfg{256, 0, 4, 8, 1};   // lanes chosen per instance
     bool bcfg_dirty = false;
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }

@@ -139,7 +139,8 @@ __device__ __forceinline__ void twosum_merge(float& s, float& c, float s2, float
 
 // One workgroup of kWeightsThreads threads computes the weights of one instance.
 __device__ __forceinline__ void weights_block(const float* __restrict__ S, int K, float lambda,
-                                              float* __restrict__ w, mppi_diag* __restrict__ diag)
+                                              float* __restrict__ w, mppi_diag* __restrict__ diag,
+                                              int lanes)
 {
     __shared__ float sh_v[kWeightsThreads / 64];
     __shared__ int sh_i[kWeightsThreads / 64], sh_n[kWeightsThreads / 64];
@@ -173,7 +174,7 @@ __device__ __forceinline__ void weights_block(const float* __restrict__ S, int K
         int i = sh_i[0], n = sh_n[0];
         for (int q = 1; q < nw; ++q) { argmin_merge(v, i, sh_v[q], sh_i[q]); n += sh_n[q]; }
         bc_rho = v; bc_n = n;
-        diag->rho = v; diag->argmin = n > 0 ? i : -1; diag->n_finite = n;
+        diag->rho = v; diag->argmin = n > 0 ? i : -1; diag->n_finite = n; diag->lanes = lanes;
     }
     __syncthreads();
     const float rho = bc_rho;

@@ -93,9 +93,14 @@ def run_batch(lib, ctx, insts):
     return [it.outputs() for it in insts]
 
 
-def run_alone(lib, ctx, insts):
+def run_alone(lib, ctx, insts, lanes_from=None):
+    """Each instance alone; with lanes_from (batched outputs), at the lanes per sample
+    each instance reported in the batch."""
     out = []
-    for it in insts:
+    for i, it in enumerate(insts):
+        if lanes_from is not None:
+            lanes = lib.diag_from_tensor(lanes_from[i][2])["lanes"]
+            lib.mppi_set_config(ctx, it.sc.K, it.sc.N, it.sc.M, 64, lanes, 1)
         it.reset()
         it.alone(lib, ctx)
         torch.cuda.synchronize()
@@ -108,15 +113,29 @@ def assert_same(a, b):
         assert torch.equal(un1, un2) and torch.equal(ua1, ua2) and torch.equal(d1, d2)
 
 
-@pytest.mark.parametrize("lanes", [1, 2])
+@pytest.mark.parametrize("lanes", [1, 2, 0])
 def test_batch_equals_alone_bitwise(lib, ctx, lanes):
+    """Fixed lanes per sample, and lanes = 0 (chosen per instance from the batch's
+    occupancy): each instance equals its solo update at the lanes it reports."""
     insts = [Inst(lib, sc, t=3) for sc in make_fleet()]
     set_lanes(lib, ctx, insts, lanes)
     batched = run_batch(lib, ctx, insts)
-    alone = run_alone(lib, ctx, insts)
+    alone = run_alone(lib, ctx, insts, lanes_from=batched)
     assert_same(batched, alone)
-    for un, ua, d in batched:
-        assert lib.diag_from_tensor(d)["status"] == 0 and torch.isfinite(ua).all()
+    for it, (un, ua, d) in zip(insts, batched):
+        dg = lib.diag_from_tensor(d)
+        assert dg["status"] == 0 and torch.isfinite(ua).all()
+        assert dg["lanes"] == lanes if lanes else dg["lanes"] in (1, 2, 4, 8)
+    if lanes == 0:   # a small mix: instances with many obstacles get more than one lane
+        assert max(lib.diag_from_tensor(d)["lanes"] for _, _, d in batched) > 1
+
+
+def test_auto_lanes_fall_to_one_when_the_batch_fills_the_chip(lib, ctx):
+    fleet = make_fleet(seed=51, shapes=[(16384, 20, 200)] * 6, paper_model_every=0)
+    insts = [Inst(lib, sc) for sc in fleet]
+    set_lanes(lib, ctx, insts, 0)
+    batched = run_batch(lib, ctx, insts)
+    assert all(lib.diag_from_tensor(d)["lanes"] == 1 for _, _, d in batched)
 
 
 def test_graph_replays_equal_eager_launches(lib, ctx):
@@ -198,6 +217,5 @@ def test_batch_autotune(lib, ctx):
     print("batch autotune", best)
     assert best["lanes"] in (1, 2, 4) and best["block"] in (64, 128, 256)
     assert lib.mppi_batch_get_config(ctx) == best
-    for it in insts:
-        lib.mppi_set_config(ctx, it.sc.K, it.sc.N, it.sc.M, 64, best["lanes"], 1)
-    assert_same(run_batch(lib, ctx, insts), run_alone(lib, ctx, insts))
+    batched = run_batch(lib, ctx, insts)
+    assert_same(batched, run_alone(lib, ctx, insts, lanes_from=batched))

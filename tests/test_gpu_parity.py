@@ -238,7 +238,7 @@ def stage_check(lib, ctx, orc, P, lam):
 
     S64 = S.double().cpu().numpy()
     w_o, d_o = orc.weights(S64, float(np.float32(lam)))
-    assert dg["status"] == 0 and dg["n_finite"] == K
+    assert dg["status"] == 0 and dg["n_finite"] == K and dg["lanes"] == 0   # stage call
     assert dg["rho"] == S64.min() and dg["argmin"] == int(d_o[3])          # same binary32 costs
     assert rel_err(dg["eta"], d_o[1], 1.0) <= TOL and rel_err(dg["ess"], d_o[2], 1.0) <= TOL
     e_w = rel_err(w.double().cpu().numpy(), w_o, 1.0 / K).max()

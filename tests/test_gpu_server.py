@@ -47,7 +47,7 @@ def new_server(lib, n_veh, n_streams=2, max_batch=4, budget=64 << 20, N_max=64):
     veh, cost = W.vehicle_benchmark(), W.cost_benchmark()
     srv = lib.Server(veh, cost, W.hover_control(veh), n_vehicles=n_veh, K_max=2048, N_max=N_max,
                      M_max=40, n_streams=n_streams, max_batch=max_batch, budget_bytes=budget)
-    srv.set_batch_config(256, 1, 4, 4)
+    srv.set_batch_config(256, 0, 4, 4)           # lanes chosen per instance
     return srv
 
 
@@ -67,7 +67,7 @@ def replay_alone(lib, reqs, results, n_veh, N_max=64, warm=None, t0=None):
     for r, res in zip(reqs, results):
         v, K, N = r["vid"], r["K"], r["N"]
         M = r["obs"].shape[0]
-        lib.mppi_set_config(ctx, K, N, M, 64, 1, 1)
+        lib.mppi_set_config(ctx, K, N, M, 64, res["lanes"], 1)
         solve = dict(K=K, N=N, dt=r["dt"], lam=r["lam"], sigma=r["sigma"], u_init=u_init,
                      seed=r["seed"], vehicle_id=v, t=res["t"])
         u_apply = torch.empty(8, device="cuda")
