@@ -79,8 +79,9 @@ class Inst:
 
 def set_lanes(lib, ctx, insts, lanes, block=256, bpc=4, use_graph=True):
     lib.mppi_batch_set_config(ctx, block, lanes, 4, bpc, use_graph)
-    for it in insts:
-        lib.mppi_set_config(ctx, it.sc.K, it.sc.N, it.sc.M, 64, lanes, 1)
+    if lanes > 0:
+        for it in insts:
+            lib.mppi_set_config(ctx, it.sc.K, it.sc.N, it.sc.M, 64, lanes, 1)
 
 
 def run_batch(lib, ctx, insts):
