@@ -285,9 +285,12 @@ def test_full_update_equals_stages_and_is_deterministic(lib, ctx, orc):
                         diag)
         torch.cuda.synchronize()
         outs.append((u_nom.cpu(), u_apply.cpu(), diag.cpu()))
+    d_s = lib.diag_from_tensor(diag_s)
     for u_nom, u_apply, diag in outs:
         assert torch.equal(u_nom.view(-1), u_nom_s.cpu()) and torch.equal(u_apply, u_apply_s.cpu())
-        assert torch.equal(diag, diag_s.cpu())
+        d = lib.diag_from_tensor(diag)
+        assert d["lanes"] == lib.mppi_get_config(ctx, P.K, P.N, P.M)["lanes"]
+        assert {k: v for k, v in d.items() if k != "lanes"} == {k: v for k, v in d_s.items() if k != "lanes"}
 
 
 def test_end_to_end_update_when_kappa_small(lib, ctx, orc):
