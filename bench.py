@@ -48,7 +48,8 @@ FLOP_STEP_BASE = {
     "perturb": 4,         # u = u_nom + du
     "input_cost": 28,     # u^T R u (12) and du^T R_d du (16)
     "controller": 40,     # Eqs. (8)-(12): rates, torques, Gamma^-1, clip
-    "rk4": 516,           # 4 x 70 derivative + 221 stage combinations + 12 renorm + 3
+    "rk4": 425,           # stage wrenches 50, 4 x 51 body derivative, 130 stage combinations,
+                          # 19 position (sum of stage accelerations), 12 renorm, 8 lag, 2
     "tracking": 44,       # Eq. (18) with Eq. (21)
     "obstacle_epilogue": 2,
     "accumulate": 5,      # Kahan add and the step sum

@@ -94,6 +94,12 @@ ModelParams model_params(const mppi_vehicle& v, float dt)
     P.T_max = v.T_max;
     P.lag = v.tau_m > 0.0f ? 1 : 0;
     P.tau_inv = P.lag ? (float)(1.0 / v.tau_m) : 0.0f;
+    if (P.lag) {
+        const double z = (double)dt / (double)v.tau_m;
+        const double c1 = 0.5 * z, c2 = c1 * (1.0 - c1), c3 = z * (1.0 - c2);
+        const double c4 = z * (6.0 - 2.0 * c1 - 2.0 * c2 - c3) / 6.0;
+        P.lag_c[0] = (float)c1; P.lag_c[1] = (float)c2; P.lag_c[2] = (float)c3; P.lag_c[3] = (float)c4;
+    }
     P.k_w = v.k_rate > 0.0f ? v.k_rate : (float)(1.0 / dt);
     P.dt = dt;
     P.w_xy_max = v.w_xy_max;

@@ -29,6 +29,12 @@ struct ModelParams {
     float T_min, T_max;
     float tau_inv;   // 1 / tau_m (rotor lag); unused when lag == 0
     int lag;         // 0: thrusts equal the clipped command (Eq. (13))
+    // RK4 applied to the linear lag T' = (T_cmd - T)/tau_m with T_cmd held gives the
+    // thrusts T + c (T_cmd - T) at RK4 stages 2, 3, 4 (c = lag_c[0..2]) and at the end
+    // of the step (c = lag_c[3]); with z = dt/tau_m: c1 = z/2, c2 = c1 (1 - c1),
+    // c3 = z (1 - c2), c4 = z (6 - 2 c1 - 2 c2 - c3)/6 = 1 - R(-z), R the RK4
+    // stability polynomial.
+    float lag_c[4];
     float k_w;       // rate-controller gain (1/dt in Eq. (8))
     float dt;
     float w_xy_max, w_z_max;
@@ -138,74 +144,108 @@ __device__ __forceinline__ void rate_controller(const ModelParams& P, float wx, 
 // Dynamics (Eq. (6)) and RK4 (Eq. (2))
 // ---------------------------------------------------------------------------
 
-template <bool kLag>
-__device__ __forceinline__ void derivative(const ModelParams& P, const State& x, const float Tc[4],
-                                           State& d)
+// Collective thrust and body torques of four rotor thrusts, Eq. (13): [F; tau] = Gamma T.
+struct Wrench {
+    float F, tx, ty, tz;
+};
+
+__device__ __forceinline__ Wrench allocate(const ModelParams& P, float T0, float T1, float T2,
+                                           float T3)
 {
-    const float T0 = kLag ? x.T0 : Tc[0], T1 = kLag ? x.T1 : Tc[1];
-    const float T2 = kLag ? x.T2 : Tc[2], T3 = kLag ? x.T3 : Tc[3];
-    // Eq. (13): [F; tau] = Gamma T
     const float s01 = T0 + T1, s23 = T2 + T3, d10 = T1 - T0, d23 = T2 - T3;
-    const float F = s01 + s23;
-    const float tx = P.s * (d10 + d23), ty = P.s * (d10 - d23), tz = P.c * (s23 - s01);
-    // p' = v
-    d.px = x.vx; d.py = x.vy; d.pz = x.vz;
-    // q' = 1/2 q (x) [0, omega]
-    const float hx = 0.5f * x.wx, hy = 0.5f * x.wy, hz = 0.5f * x.wz;
-    d.qw = -(x.qx * hx + x.qy * hy + x.qz * hz);
-    d.qx = x.qw * hx + x.qy * hz - x.qz * hy;
-    d.qy = x.qw * hy - x.qx * hz + x.qz * hx;
-    d.qz = x.qw * hz + x.qx * hy - x.qy * hx;
-    // v' = R(q) [0, 0, F] / m + [0, 0, -g]; third column of R(q)
-    const float fm = F * P.m_inv, f2 = fm + fm;
-    d.vx = f2 * (x.qx * x.qz + x.qw * x.qy);
-    d.vy = f2 * (x.qy * x.qz - x.qw * x.qx);
-    d.vz = fm - f2 * (x.qx * x.qx + x.qy * x.qy) - P.g;
-    // omega' = J^-1 (tau - omega x J omega)
-    d.wx = (tx - P.G[0] * (x.wy * x.wz)) * P.J_inv[0];
-    d.wy = (ty - P.G[1] * (x.wz * x.wx)) * P.J_inv[1];
-    d.wz = (tz - P.G[2] * (x.wx * x.wy)) * P.J_inv[2];
-    // rotor lag T' = (T_cmd - T) / tau_m
-    if (kLag) {
-        d.T0 = (Tc[0] - x.T0) * P.tau_inv;
-        d.T1 = (Tc[1] - x.T1) * P.tau_inv;
-        d.T2 = (Tc[2] - x.T2) * P.tau_inv;
-        d.T3 = (Tc[3] - x.T3) * P.tau_inv;
-    } else {
-        d.T0 = d.T1 = d.T2 = d.T3 = 0.0f;
-    }
+    return Wrench{s01 + s23, P.s * (d10 + d23), P.s * (d10 - d23), P.c * (s23 - s01)};
 }
 
-#define MPPI_STATE_FIELDS(X) \
-    X(px) X(py) X(pz) X(qw) X(qx) X(qy) X(qz) X(vx) X(vy) X(vz) X(wx) X(wy) X(wz) \
-    X(T0) X(T1) X(T2) X(T3)
+// Attitude, velocity and body rate: the part of the state the right-hand side of
+// Eq. (6) depends on (it does not depend on the position).
+struct Body {
+    float qw, qx, qy, qz;
+    float vx, vy, vz;
+    float wx, wy, wz;
+};
+
+#define MPPI_BODY_FIELDS(X) X(qw) X(qx) X(qy) X(qz) X(vx) X(vy) X(vz) X(wx) X(wy) X(wz)
+
+__device__ __forceinline__ void body_derivative(const ModelParams& P, const Body& b, const Wrench& W,
+                                                Body& d)
+{
+    // q' = 1/2 q (x) [0, omega]
+    const float hx = 0.5f * b.wx, hy = 0.5f * b.wy, hz = 0.5f * b.wz;
+    d.qw = -(b.qx * hx + b.qy * hy + b.qz * hz);
+    d.qx = b.qw * hx + b.qy * hz - b.qz * hy;
+    d.qy = b.qw * hy - b.qx * hz + b.qz * hx;
+    d.qz = b.qw * hz + b.qx * hy - b.qy * hx;
+    // v' = R(q) [0, 0, F] / m + [0, 0, -g]; third column of R(q)
+    const float fm = W.F * P.m_inv, f2 = fm + fm;
+    d.vx = f2 * (b.qx * b.qz + b.qw * b.qy);
+    d.vy = f2 * (b.qy * b.qz - b.qw * b.qx);
+    d.vz = fm - f2 * (b.qx * b.qx + b.qy * b.qy) - P.g;
+    // omega' = J^-1 (tau - omega x J omega)
+    d.wx = (W.tx - P.G[0] * (b.wy * b.wz)) * P.J_inv[0];
+    d.wy = (W.ty - P.G[1] * (b.wz * b.wx)) * P.J_inv[1];
+    d.wz = (W.tz - P.G[2] * (b.wx * b.wy)) * P.J_inv[2];
+}
 
 // One step x <- x + f_RK4(x, Tc, dt) with the command held, then q <- q / |q|.
+// This is classic RK4 on the 17-value state, arranged to skip work that is known in
+// closed form: the wrench at each stage point comes from the stage thrusts of the
+// linear lag (W(T) + c_s W(T_cmd - T), exact since the allocation is linear), and
+// since nothing depends on the position its update is p + h v + h^2/6 (a1 + a2 + a3),
+// which is what RK4's four stage velocities sum to.
 template <bool kLag>
 __device__ __forceinline__ void rk4_step(const ModelParams& P, State& x, const float Tc[4])
 {
     const float h = P.dt, h2 = 0.5f * P.dt, h6 = P.dt * (1.0f / 6.0f);
-    State k, xs, acc;
-    derivative<kLag>(P, x, Tc, k);                               // k1
-#define STAGE1(f) acc.f = k.f; xs.f = fmaf(h2, k.f, x.f);
-    MPPI_STATE_FIELDS(STAGE1)
+    Wrench W1, W2, W3, W4;
+    float D0 = 0.0f, D1 = 0.0f, D2 = 0.0f, D3 = 0.0f;
+    if (kLag) {
+        D0 = Tc[0] - x.T0; D1 = Tc[1] - x.T1; D2 = Tc[2] - x.T2; D3 = Tc[3] - x.T3;
+        const Wrench W0 = allocate(P, x.T0, x.T1, x.T2, x.T3);
+        const Wrench dW = allocate(P, D0, D1, D2, D3);
+        W1 = W0;
+#define MPPI_STAGE_WRENCH(Ws, c) \
+        Ws = Wrench{fmaf(c, dW.F, W0.F), fmaf(c, dW.tx, W0.tx), fmaf(c, dW.ty, W0.ty), fmaf(c, dW.tz, W0.tz)};
+        MPPI_STAGE_WRENCH(W2, P.lag_c[0])
+        MPPI_STAGE_WRENCH(W3, P.lag_c[1])
+        MPPI_STAGE_WRENCH(W4, P.lag_c[2])
+#undef MPPI_STAGE_WRENCH
+    } else {
+        W1 = W2 = W3 = W4 = allocate(P, Tc[0], Tc[1], Tc[2], Tc[3]);
+    }
+    const Body b{x.qw, x.qx, x.qy, x.qz, x.vx, x.vy, x.vz, x.wx, x.wy, x.wz};
+    Body k, bs, acc;
+    body_derivative(P, b, W1, k);                                // k1
+    float ax = k.vx, ay = k.vy, az = k.vz;
+#define STAGE1(f) acc.f = k.f; bs.f = fmaf(h2, k.f, b.f);
+    MPPI_BODY_FIELDS(STAGE1)
 #undef STAGE1
-    derivative<kLag>(P, xs, Tc, k);                              // k2
-#define STAGE2(f) acc.f = fmaf(2.0f, k.f, acc.f); xs.f = fmaf(h2, k.f, x.f);
-    MPPI_STATE_FIELDS(STAGE2)
+    body_derivative(P, bs, W2, k);                               // k2
+    ax += k.vx; ay += k.vy; az += k.vz;
+#define STAGE2(f) acc.f = fmaf(2.0f, k.f, acc.f); bs.f = fmaf(h2, k.f, b.f);
+    MPPI_BODY_FIELDS(STAGE2)
 #undef STAGE2
-    derivative<kLag>(P, xs, Tc, k);                              // k3
-#define STAGE3(f) acc.f = fmaf(2.0f, k.f, acc.f); xs.f = fmaf(h, k.f, x.f);
-    MPPI_STATE_FIELDS(STAGE3)
+    body_derivative(P, bs, W3, k);                               // k3
+    ax += k.vx; ay += k.vy; az += k.vz;
+#define STAGE3(f) acc.f = fmaf(2.0f, k.f, acc.f); bs.f = fmaf(h, k.f, b.f);
+    MPPI_BODY_FIELDS(STAGE3)
 #undef STAGE3
-    derivative<kLag>(P, xs, Tc, k);                              // k4
-#define STAGE4(f) x.f = fmaf(h6, acc.f + k.f, x.f);
-    MPPI_STATE_FIELDS(STAGE4)
+    body_derivative(P, bs, W4, k);                               // k4
+    const float hh6 = h * h6;
+    x.px = fmaf(hh6, ax, fmaf(h, b.vx, x.px));
+    x.py = fmaf(hh6, ay, fmaf(h, b.vy, x.py));
+    x.pz = fmaf(hh6, az, fmaf(h, b.vz, x.pz));
+#define STAGE4(f) x.f = fmaf(h6, acc.f + k.f, b.f);
+    MPPI_BODY_FIELDS(STAGE4)
 #undef STAGE4
     const float n2 = x.qw * x.qw + x.qx * x.qx + x.qy * x.qy + x.qz * x.qz;
     const float inv = __builtin_amdgcn_rsqf(n2);
     x.qw *= inv; x.qx *= inv; x.qy *= inv; x.qz *= inv;
-    if (!kLag) { x.T0 = Tc[0]; x.T1 = Tc[1]; x.T2 = Tc[2]; x.T3 = Tc[3]; }
+    if (kLag) {
+        x.T0 = fmaf(P.lag_c[3], D0, x.T0); x.T1 = fmaf(P.lag_c[3], D1, x.T1);
+        x.T2 = fmaf(P.lag_c[3], D2, x.T2); x.T3 = fmaf(P.lag_c[3], D3, x.T3);
+    } else {
+        x.T0 = Tc[0]; x.T1 = Tc[1]; x.T2 = Tc[2]; x.T3 = Tc[3];
+    }
 }
 
 // ---------------------------------------------------------------------------
