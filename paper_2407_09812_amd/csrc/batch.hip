@@ -27,7 +27,6 @@ template <int L, int U>
 __device__ __forceinline__ void batch_tile(const InstanceDesc& D, int k0, const float4* obs_lds)
 {
     const int k = k0 + (int)threadIdx.x / L, q = (int)threadIdx.x % L;
-    if (k >= D.rp.K) return;
     if (D.rp.mp.lag)
         rollout_sample<L, U, true, false>(D.rp, D.x_hat, D.x_ref, D.u_nom, D.du, D.S, nullptr,
                                           obs_lds, k, q);

@@ -159,7 +159,7 @@ const WorkItem* dev_items(const BatchState& b)
     return reinterpret_cast<const WorkItem*>(static_cast<char*>(b.plan_dev) +
                                              plan_layout(b.n_cap, b.items_cap).items_off);
 }
-int lds_bytes(const BatchState& b) { return (int)(2 * sizeof(float4) * (size_t)std::max(b.M_cap, 1)); }
+int lds_bytes(const BatchState& b) { return (int)obstacle_lds_bytes(std::max(b.M_cap, 1)); }
 
 mppi_status capacity_ok(mppi_ctx* ctx, const Needs& nd)
 {

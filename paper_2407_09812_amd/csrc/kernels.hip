@@ -23,13 +23,12 @@ __global__ __launch_bounds__(256) void rollout_kernel(
     const mppi_obstacle* __restrict__ obs, const float* __restrict__ u_nom,
     float* __restrict__ du_out, float* __restrict__ S_out, float* __restrict__ states)
 {
-    extern __shared__ float4 obs_lds[];   // 2 x M float4
+    extern __shared__ float4 obs_lds[];   // obstacle_lds_bytes(M)
     stage_obstacles(obs_lds, obs, a.M, x_hat[0], x_hat[1], x_hat[2], a.cp.margin);
     __syncthreads();
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = g / L, q = g % L;
-    if (k >= a.K) return;
-    rollout_sample<L, U, kLag, kDump>(a, x_hat, x_ref, u_nom, du_out, S_out, states, obs_lds, k, q);
+    rollout_sample<L, U, kLag, kDump>(a, x_hat, x_ref, u_nom, du_out, S_out, states, obs_lds, g / L,
+                                      g % L);
 }
 
 __global__ __launch_bounds__(kWeightsThreads) void weights_kernel(const float* __restrict__ S, int K,
@@ -116,7 +115,7 @@ static hipError_t launch_rollout_lu(const RolloutArgs& a, int block, hipStream_t
 {
     const size_t threads = (size_t)a.K * L;
     const int grid = (int)((threads + block - 1) / block);
-    const size_t lds = sizeof(float4) * 2 * (size_t)a.M;
+    const size_t lds = obstacle_lds_bytes(a.M);
     const RolloutParams p{a.mp, a.cp, a.np, a.M, a.K, a.N, a.ld};
     auto kernel = a.mp.lag ? (a.states ? rollout_kernel<L, U, true, true> : rollout_kernel<L, U, true, false>)
                            : (a.states ? rollout_kernel<L, U, false, true> : rollout_kernel<L, U, false, false>);

@@ -290,19 +290,70 @@ __device__ __forceinline__ float group_sum(float v)
     return v;
 }
 
-// Obstacles staged in LDS as two float4 per obstacle:
-//   a = (cx, cy, cz, zmask)  centre relative to the frame origin; zmask 0 for a
-//                            vertical cylinder (ignore z), 1 for a sphere
-//   b = (r^2, (r + margin)^2, r + margin, 0)
-// Lane q of a sample's L lanes tests obstacles q, q + L, q + 2L, ...; the partial
-// penalties and hit flags are then combined over the group.
+// Minimum / maximum over the 64 lanes of the wave (all lanes active), returned in a
+// scalar register: butterflies within each row of 16 (quad permutations, half-row
+// and row mirrors), then the row broadcasts 15 and 31 fold rows into lane 63.
+template <bool kMax, int kCtrl, int kRowMask>
+__device__ __forceinline__ float dpp_extreme_step(float x)
+{
+    const float y = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x),
+                                                               kCtrl, kRowMask, 0xF, false));
+    return kMax ? fmaxf(x, y) : fminf(x, y);
+}
+
+template <bool kMax>
+__device__ __forceinline__ float wave_extreme(float v)
+{
+    v = dpp_extreme_step<kMax, 0xB1, 0xF>(v);     // quad_perm [1, 0, 3, 2]
+    v = dpp_extreme_step<kMax, 0x4E, 0xF>(v);     // quad_perm [2, 3, 0, 1]
+    v = dpp_extreme_step<kMax, 0x141, 0xF>(v);    // row_half_mirror
+    v = dpp_extreme_step<kMax, 0x140, 0xF>(v);    // row_mirror
+    v = dpp_extreme_step<kMax, 0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
+    v = dpp_extreme_step<kMax, 0x143, 0xC>(v);    // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// Obstacles in LDS, one block per workgroup (see stage_obstacles):
+//   float4 header (x0, 1 / bin width, R_max + slack, culling on)
+//   kObsBins + 1 bin starts (int, padded to 68): first obstacle with x >= x0 + b w
+//   two float4 per obstacle, sorted by x:
+//     a = (cx, cy, cz, zmask)  centre relative to the frame origin; zmask 0 for a
+//                              vertical cylinder (ignore z), 1 for a sphere
+//     b = (r^2, (r + margin)^2, r + margin, 0)
+constexpr int kObsBins = 64;
+constexpr int kObsHeaderFloat4 = 1 + 68 / 4;        // header + padded bin table
+constexpr int kCullMin = 16, kCullMax = 512;       // sorted and culled for M in this range
+constexpr float kCullSlack = 1.0e-3f;              // m, covers rounding of the x tests
+
+__host__ __device__ constexpr size_t obstacle_lds_bytes(int M)
+{
+    return sizeof(float4) * (size_t)(kObsHeaderFloat4 + 2 * (M > 0 ? M : 0));
+}
+
+// Obstacle term of Eq. (22) (with the quadratic margin) for this lane's position.
+// Lane q of a sample's L lanes tests obstacles q, q + L, ...; the partial penalties and
+// hit flags are combined over the group.  With culling on, the wave first takes the
+// x-range of all its lanes' positions and tests only obstacles whose centre lies
+// within R_max + slack of that range: every other obstacle is farther than its
+// r + margin from every lane, so it adds exactly zero to the penalty and to the hit.
 template <int L, int U>
 __device__ __forceinline__ float obstacle_cost(const CostParams& C, float px, float py, float pz,
-                                               const float4* __restrict__ obs, int M, int q)
+                                               const float4* __restrict__ blk, int M, int q)
 {
+    const float4 h = blk[0];
+    const int* bins = reinterpret_cast<const int*>(blk + 1);
+    const float4* obs = blk + kObsHeaderFloat4;
+    int i0 = 0, i1 = M;
+    if (h.w != 0.0f) {
+        const float lo = wave_extreme<false>(px) - h.z, hi = wave_extreme<true>(px) + h.z;
+        const float b0 = fminf(fmaxf(floorf((lo - h.x) * h.y), 0.0f), (float)kObsBins);
+        const float b1 = fminf(fmaxf(floorf((hi - h.x) * h.y) + 1.0f, 0.0f), (float)kObsBins);
+        i0 = __builtin_amdgcn_readfirstlane(bins[(int)b0]);
+        i1 = __builtin_amdgcn_readfirstlane(bins[(int)b1]);
+    }
     float hit = 0.0f, pen = 0.0f;
 #pragma unroll U
-    for (int i = q; i < M; i += L) {
+    for (int i = i0 + q; i < i1; i += L) {
         const float4 a = obs[2 * i], b = obs[2 * i + 1];
         const float dx = px - a.x, dy = py - a.y, dz = (pz - a.z) * a.w;
         const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));

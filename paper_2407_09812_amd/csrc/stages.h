@@ -17,26 +17,69 @@ namespace mppi {
 // Rollouts and costs (Eqs. (2), (3), (16)-(22))
 // ---------------------------------------------------------------------------
 
-// Stage the obstacle list into LDS (cooperatively; the caller synchronises),
+// Stage the obstacle list into the workgroup's LDS block (layout at obstacle_cost),
 // centred on x_hat's position: the rollouts integrate positions relative to p_hat,
 // which keeps binary32 rounding at the scale of the excursion rather than of the
-// world frame.
-__device__ __forceinline__ void stage_obstacles(float4* obs_lds, const mppi_obstacle* __restrict__ obs,
+// world frame.  For kCullMin <= M <= kCullMax the obstacles are placed in order of x
+// (rank sort: each obstacle's rank is the number of obstacles before it in (x, index)
+// order) and indexed by kObsBins bins; otherwise they keep their order and culling is
+// off.  Contains barriers: every thread of the workgroup calls it; the caller
+// synchronises again before reading the block.
+__device__ __forceinline__ void stage_obstacles(float4* blk, const mppi_obstacle* __restrict__ obs,
                                                 int M, float phx, float phy, float phz, float margin)
 {
+    __shared__ unsigned int s_rmax;
+    float4* o_lds = blk + kObsHeaderFloat4;
+    int* bins = reinterpret_cast<int*>(blk + 1);
+    const bool cull = M >= kCullMin && M <= kCullMax;
+    if (threadIdx.x == 0) s_rmax = 0u;
+    __syncthreads();
     for (int i = threadIdx.x; i < M; i += blockDim.x) {
         const mppi_obstacle o = obs[i];
+        const float key = o.c[0] - phx;
+        int rank = i;
+        if (cull) {
+            rank = 0;
+            for (int j = 0; j < M; ++j) {
+                const float kj = obs[j].c[0] - phx;
+                rank += (kj < key || (kj == key && j < i)) ? 1 : 0;
+            }
+        }
         const float R = o.r + margin;
-        obs_lds[2 * i] = make_float4(o.c[0] - phx, o.c[1] - phy, o.c[2] - phz,
-                                     o.type == MPPI_VCYLINDER ? 0.0f : 1.0f);
-        obs_lds[2 * i + 1] = make_float4(o.r * o.r, R * R, R, 0.0f);
+        o_lds[2 * rank] = make_float4(key, o.c[1] - phy, o.c[2] - phz,
+                                      o.type == MPPI_VCYLINDER ? 0.0f : 1.0f);
+        o_lds[2 * rank + 1] = make_float4(o.r * o.r, R * R, R, 0.0f);
+        atomicMax(&s_rmax, __float_as_uint(fmaxf(R, 0.0f)));
     }
+    __syncthreads();
+    float x0 = 0.0f, w = 1.0f;
+    if (cull) {
+        x0 = o_lds[0].x;
+        w = fmaxf((o_lds[2 * (M - 1)].x - x0) * (1.0f / kObsBins), 1.0e-3f);
+        for (int bb = threadIdx.x; bb <= kObsBins; bb += blockDim.x) {
+            int idx = M;
+            if (bb < kObsBins) {                     // first obstacle with x >= x0 + bb w
+                const float edge = x0 + (float)bb * w;
+                int lo = 0, hi = M;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (o_lds[2 * mid].x < edge) lo = mid + 1; else hi = mid;
+                }
+                idx = lo;
+            }
+            bins[bb] = idx;
+        }
+    }
+    if (threadIdx.x == 0)
+        blk[0] = make_float4(x0, 1.0f / w, __uint_as_float(s_rmax) + kCullSlack, cull ? 1.0f : 0.0f);
 }
 
 // Rollout of sample k by lane q of its L lanes.  The L lanes integrate the same
 // sample (identical instructions and operands, hence identical trajectories) and
-// divide its obstacle tests; lane q = 0 writes delta_u [N][4][ld], S [K] and the
-// optional trajectory dump [N+1][17][ld] (world-frame positions).
+// divide its obstacle tests; lane q = 0 of a valid sample writes delta_u [N][4][ld],
+// S [K] and the optional trajectory dump [N+1][17][ld] (world-frame positions).
+// Lanes past the last sample run a copy of sample K-1 without writing, so that
+// every lane of the wave takes part in the wave-wide obstacle culling.
 template <int L, int U, bool kLag, bool kDump>
 __device__ __forceinline__ void rollout_sample(const RolloutParams& a, const float* __restrict__ x_hat,
                                                const float* __restrict__ x_ref,
@@ -45,7 +88,8 @@ __device__ __forceinline__ void rollout_sample(const RolloutParams& a, const flo
                                                float* __restrict__ states,
                                                const float4* __restrict__ obs_lds, int k, int q)
 {
-    const bool writer = (q == 0);
+    const bool writer = (q == 0) && k < a.K;
+    if (k >= a.K) k = a.K - 1;
     const size_t ld = (size_t)a.ld;
     const float phx = x_hat[0], phy = x_hat[1], phz = x_hat[2];
 
