@@ -54,16 +54,25 @@ FLOP_STEP_BASE = {
     "obstacle_epilogue": 2,
     "accumulate": 5,      # Kahan add and the step sum
 }
-FLOP_PER_OBSTACLE = 11     # 2 sub, sub + mul (z mask), mul + 2 fma, 2 compares
+FLOP_PER_OBSTACLE_TEST = 11   # 2 sub, sub + mul (z mask), mul + 2 fma, 2 compares
+FLOP_CULL_PER_STATE = 28       # wave x-range (2 x 6 DPP min/max), range bounds, bin lookups
+FLOP_INITIAL_STATE = 44 + 2 + 5  # scoring of x_hat itself (tracking, obstacle epilogue, sum)
 
 
-def flop_per_rollout_step(M: int) -> int:
-    return sum(FLOP_STEP_BASE.values()) + FLOP_PER_OBSTACLE * M
+def flop_per_rollout_step() -> int:
+    return sum(FLOP_STEP_BASE.values())
 
 
-def rollout_flop_per_launch(K: int, N: int, M: int) -> float:
-    # N steps plus the scoring of the initial state (tracking + obstacles)
-    return float(K) * (N * flop_per_rollout_step(M) + 44 + FLOP_PER_OBSTACLE * M + 2 + 5)
+def rollout_flop_per_launch(K: int, N: int, M: int, obstacle_tests: float) -> float:
+    """Algorithmic FP32 FLOP of one rollout launch: the per-step formulation count for
+    K N sample-steps, the scoring of the initial state, the culling arithmetic when the
+    obstacles are culled (16 <= M <= 512), and 11 FLOP per obstacle distance test
+    actually performed (measured by the library's counter: obstacles outside a wave's
+    reach are skipped and cost nothing)."""
+    states = K * (N + 1)
+    cull = states * FLOP_CULL_PER_STATE if 16 <= M <= 512 else 0
+    return float(K) * N * flop_per_rollout_step() + K * FLOP_INITIAL_STATE + cull + \
+        FLOP_PER_OBSTACLE_TEST * obstacle_tests
 
 
 def reduction_bytes_per_launch(K: int, N: int) -> float:
@@ -199,7 +208,8 @@ def run(args):
     n_upd = max(1, prof["updates"])
     rollout_ms = prof["rollout_ms"] / n_upd
     reduce_ms = prof["reduce_ms"] / n_upd
-    flop = rollout_flop_per_launch(K, N, M)
+    tests = prof["obstacle_tests"] / n_upd
+    flop = rollout_flop_per_launch(K, N, M, tests)
     achieved = flop / (rollout_ms * 1e-3)
     rbytes = reduction_bytes_per_launch(K, N)
     out = {
@@ -231,6 +241,7 @@ def run(args):
             "frac": achieved / PEAK_FP32_VECTOR,
             "frac_of_unpacked_peak": achieved / PEAK_FP32_UNPACKED,
             "flop_per_launch": flop,
+            "obstacle_tests_per_state": tests / (K * (N + 1)),
             "traffic": measured_traffic(K, N, M),
         },
         "reduction": {"kernel": "weighted_sum_kernel", "bound": "hbm",
@@ -313,7 +324,6 @@ def run_batched(args, steps: int, warmup: int, plain_steps: int):
         lib.mppi_batch_get_config(ctx)
     log(f"bench: batched launch shape {cfg}")
     steps_per_batch = sum(sc.K * sc.N for sc in fleet)
-    flop_per_batch = sum(rollout_flop_per_launch(sc.K, sc.N, sc.M) for sc in fleet)
     stream = torch.cuda.current_stream()
 
     for t in range(warmup):
@@ -337,8 +347,13 @@ def run_batched(args, steps: int, warmup: int, plain_steps: int):
     torch.cuda.synchronize()
     prof = lib.mppi_profile_read(ctx)
     lib.mppi_profile_enable(ctx, False)
-    rollout_ms = prof["batch_rollout_ms"] / max(1, prof["batches"])
-    rest_ms = prof["batch_rest_ms"] / max(1, prof["batches"])
+    n_b = max(1, prof["batches"])
+    rollout_ms = prof["batch_rollout_ms"] / n_b
+    rest_ms = prof["batch_rest_ms"] / n_b
+    tests = prof["obstacle_tests"] / n_b
+    flop_per_batch = sum(rollout_flop_per_launch(sc.K, sc.N, sc.M, 0.0) for sc in fleet) + \
+        FLOP_PER_OBSTACLE_TEST * tests
+    dense_tests = sum(sc.K * (sc.N + 1) * sc.M for sc in fleet)
     du_bytes = sum(reduction_bytes_per_launch(sc.K, sc.N) for sc in fleet)
 
     # the same updates as sequential one-instance launch sequences
@@ -373,7 +388,9 @@ def run_batched(args, steps: int, warmup: int, plain_steps: int):
                      "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
                      "frac_of_unpacked_peak": achieved / PEAK_FP32_UNPACKED,
-                     "flop_per_launch": flop_per_batch},
+                     "flop_per_launch": flop_per_batch,
+                     "obstacle_tests_per_batch": tests,
+                     "obstacle_tests_fraction_of_dense": tests / max(1, dense_tests)},
         "reduction_stages": {"bytes_per_batch": du_bytes,
                              "achieved": du_bytes / (rest_ms * 1e-3) / 1e9, "unit": "GB/s",
                              "note": "weights + weighted sum + apply, bytes of the weighted sum"},

@@ -375,6 +375,8 @@ typedef struct mppi_profile {
     double rollout_ms, weights_ms, reduce_ms, apply_ms;
     int64_t batches;
     double batch_rollout_ms, batch_rest_ms;
+    int64_t obstacle_tests;   /* sample-state-obstacle distance tests performed (both paths);
+                                 obstacles out of a wave's reach are skipped, see DESIGN */
 } mppi_profile;
 
 mppi_status mppi_profile_enable(mppi_ctx *ctx, int32_t on);

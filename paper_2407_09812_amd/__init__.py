@@ -109,7 +109,8 @@ class ServerStats(C.Structure):
 class Profile(C.Structure):
     _fields_ = [("updates", C.c_int64), ("rollout_ms", C.c_double), ("weights_ms", C.c_double),
                 ("reduce_ms", C.c_double), ("apply_ms", C.c_double), ("batches", C.c_int64),
-                ("batch_rollout_ms", C.c_double), ("batch_rest_ms", C.c_double)]
+                ("batch_rollout_ms", C.c_double), ("batch_rest_ms", C.c_double),
+                ("obstacle_tests", C.c_int64)]
 
 
 OBSTACLE_DTYPE = np.dtype([("type", "<i4"), ("c", "<f4", (3,)), ("r", "<f4")])
@@ -420,7 +421,8 @@ def mppi_profile_read(ctx) -> dict:
     ctx.check(_lib.mppi_profile_read(ctx.handle, C.byref(p)), "mppi_profile_read")
     return dict(updates=p.updates, rollout_ms=p.rollout_ms, weights_ms=p.weights_ms,
                 reduce_ms=p.reduce_ms, apply_ms=p.apply_ms, batches=p.batches,
-                batch_rollout_ms=p.batch_rollout_ms, batch_rest_ms=p.batch_rest_ms)
+                batch_rollout_ms=p.batch_rollout_ms, batch_rest_ms=p.batch_rest_ms,
+                obstacle_tests=p.obstacle_tests)
 
 
 def mppi_status_str(st: int) -> str:

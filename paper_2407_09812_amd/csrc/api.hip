@@ -259,6 +259,7 @@ mppi_status mppi_destroy(mppi_ctx* ctx)
     (void)hipDeviceSynchronize();
     free_scratch(ctx);
     free_batch(ctx);
+    (void)hipFree(ctx->obs_tests);
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->pending) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->batch_pending) (void)hipEventDestroy(e);
@@ -313,6 +314,7 @@ mppi_status mppi_update(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh, co
     RolloutArgs a = rollout_args(*veh, *cost, *solve);
     a.x_hat = x_hat; a.x_ref = x_ref; a.obs = obs; a.M = M; a.u_nom = u_nom;
     a.du = ctx->du; a.ld = ctx->ld; a.S = ctx->S; a.states = nullptr;
+    a.obs_tests = ctx->profiling ? ctx->obs_tests : nullptr;
 
     hipEvent_t ev[kEventsPerUpdate] = {};
     if (ctx->profiling)
@@ -499,6 +501,11 @@ mppi_status mppi_plant_step(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh
 mppi_status mppi_profile_enable(mppi_ctx* ctx, int32_t on)
 {
     if (!ctx) return MPPI_E_INVALID_ARG;
+    if (on && !ctx->obs_tests) {
+        HIP_TRY(ctx, hipMalloc(&ctx->obs_tests, sizeof(unsigned long long)));
+        HIP_TRY(ctx, hipMemset(ctx->obs_tests, 0, sizeof(unsigned long long)));
+        HIP_TRY(ctx, hipDeviceSynchronize());
+    }
     ctx->profiling = on != 0;
     return MPPI_OK;
 }
@@ -531,6 +538,14 @@ mppi_status mppi_profile_read(mppi_ctx* ctx, mppi_profile* out)
     }
     for (hipEvent_t e : ctx->batch_pending) ctx->pool.push_back(e);
     ctx->batch_pending.clear();
+    if (ctx->obs_tests) {
+        unsigned long long n = 0;
+        HIP_TRY(ctx, hipDeviceSynchronize());
+        HIP_TRY(ctx, hipMemcpy(&n, ctx->obs_tests, sizeof(n), hipMemcpyDeviceToHost));
+        HIP_TRY(ctx, hipMemset(ctx->obs_tests, 0, sizeof(n)));
+        HIP_TRY(ctx, hipDeviceSynchronize());
+        ctx->acc.obstacle_tests += (int64_t)n;
+    }
     *out = ctx->acc;
     ctx->acc = mppi_profile{};
     return MPPI_OK;

@@ -102,6 +102,7 @@ size_t fill_plan(mppi_ctx* ctx, const mppi_request* reqs, int n, const BatchLaun
         D.rp.cp = cost_params(q.cost);
         D.rp.np = noise_params(q.solve);
         D.rp.M = q.M; D.rp.K = K; D.rp.N = N; D.rp.ld = ld;
+        D.rp.obs_tests = ctx->profiling ? ctx->obs_tests : nullptr;
         D.lambda = q.solve.lambda;
         for (int d = 0; d < 4; ++d) D.u_init[d] = q.solve.u_init[d];
         D.row0 = row;

@@ -53,6 +53,7 @@ struct mppi_ctx {
     bool profiling = false;
     std::vector<hipEvent_t> pool, pending, batch_pending;   // 5 per update, 3 per batch
     mppi_profile acc{};
+    unsigned long long* obs_tests = nullptr;   // device counter while profiling
     mppi::BatchState batch;
 };
 

@@ -25,6 +25,7 @@ struct RolloutArgs {
     int ld;
     float* S;                    // K
     float* states;               // [N+1][17][ld] or nullptr
+    unsigned long long* obs_tests;   // obstacle-test counter or nullptr
 };
 
 

@@ -116,7 +116,7 @@ static hipError_t launch_rollout_lu(const RolloutArgs& a, int block, hipStream_t
     const size_t threads = (size_t)a.K * L;
     const int grid = (int)((threads + block - 1) / block);
     const size_t lds = obstacle_lds_bytes(a.M);
-    const RolloutParams p{a.mp, a.cp, a.np, a.M, a.K, a.N, a.ld};
+    const RolloutParams p{a.mp, a.cp, a.np, a.M, a.K, a.N, a.ld, a.obs_tests};
     auto kernel = a.mp.lag ? (a.states ? rollout_kernel<L, U, true, true> : rollout_kernel<L, U, true, false>)
                            : (a.states ? rollout_kernel<L, U, false, true> : rollout_kernel<L, U, false, false>);
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), lds, stream, p, a.x_hat, a.x_ref, a.obs,

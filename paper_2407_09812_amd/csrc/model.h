@@ -52,12 +52,14 @@ struct NoiseParams {
     uint32_t t, seed_hi;    // counter words 2 and 3
 };
 
-// Scalar parameters of one instance's rollout launch.
+// Scalar parameters of one instance's rollout launch.  obs_tests, when not null,
+// accumulates the number of obstacle tests the launch performed (profiling).
 struct RolloutParams {
     ModelParams mp;
     CostParams cp;
     NoiseParams np;
     int M, K, N, ld;
+    unsigned long long* obs_tests;
 };
 
 constexpr int kWeightsThreads = 1024;   // one workgroup computes one instance's weights
@@ -338,7 +340,8 @@ __host__ __device__ constexpr size_t obstacle_lds_bytes(int M)
 // r + margin from every lane, so it adds exactly zero to the penalty and to the hit.
 template <int L, int U>
 __device__ __forceinline__ float obstacle_cost(const CostParams& C, float px, float py, float pz,
-                                               const float4* __restrict__ blk, int M, int q)
+                                               const float4* __restrict__ blk, int M, int q,
+                                               int& tested)
 {
     const float4 h = blk[0];
     const int* bins = reinterpret_cast<const int*>(blk + 1);
@@ -351,6 +354,7 @@ __device__ __forceinline__ float obstacle_cost(const CostParams& C, float px, fl
         i0 = __builtin_amdgcn_readfirstlane(bins[(int)b0]);
         i1 = __builtin_amdgcn_readfirstlane(bins[(int)b1]);
     }
+    tested += i1 - i0;                     // obstacles each sample of this wave tests
     float hit = 0.0f, pen = 0.0f;
 #pragma unroll U
     for (int i = i0 + q; i < i1; i += L) {

@@ -108,9 +108,10 @@ __device__ __forceinline__ void rollout_sample(const RolloutParams& a, const flo
     }
 
     KahanSum S;
+    int tested = 0;
     // state j = 0 (the estimate itself) is scored like every other state (Eq. (17))
     S.add(tracking_cost(a.cp, x, x_ref[0] - phx, x_ref[1] - phy, x_ref[2] - phz, x_ref) +
-          obstacle_cost<L, U>(a.cp, x.px, x.py, x.pz, obs_lds, a.M, q));
+          obstacle_cost<L, U>(a.cp, x.px, x.py, x.pz, obs_lds, a.M, q, tested));
 
     float up[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int j = 0; j < a.N; ++j) {
@@ -143,7 +144,7 @@ __device__ __forceinline__ void rollout_sample(const RolloutParams& a, const flo
 
         const float* ref = x_ref + (size_t)13 * (j + 1);
         const float cx = tracking_cost(a.cp, x, ref[0] - phx, ref[1] - phy, ref[2] - phz, ref) +
-                         obstacle_cost<L, U>(a.cp, x.px, x.py, x.pz, obs_lds, a.M, q);
+                         obstacle_cost<L, U>(a.cp, x.px, x.py, x.pz, obs_lds, a.M, q, tested);
         S.add(cu + cx);
 
         if (kDump && writer) {
@@ -155,6 +156,10 @@ __device__ __forceinline__ void rollout_sample(const RolloutParams& a, const flo
         }
     }
     if (writer) S_out[k] = S.s;
+    if (a.obs_tests) {                     // one atomic per wave: valid samples x tests
+        const unsigned long long samples = __popcll(__ballot(writer));
+        if (__lane_id() == 0) atomicAdd(a.obs_tests, samples * (unsigned long long)tested);
+    }
 }
 
 // ---------------------------------------------------------------------------

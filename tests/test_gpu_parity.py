@@ -316,6 +316,29 @@ def test_end_to_end_update_when_kappa_small(lib, ctx, orc):
     assert e_a <= TOL and e_n <= TOL
 
 
+def test_obstacle_test_counter(lib, ctx):
+    """With profiling on, the library counts the obstacle distance tests it performs:
+    every (sample, state, obstacle) without culling (M < 16), and no more than that
+    -- here far fewer -- when the wave-range culling is on."""
+    for M, dense_only in ((10, True), (200, False)):
+        sc = W.c3_agile(K=1000, N=40)
+        sc.obstacles = sc.obstacles[:M]
+        P = DeviceProblem(lib, sc)
+        lib.mppi_reserve(ctx, P.K, P.N, M)
+        lib.mppi_profile_enable(ctx, True)
+        lib.mppi_profile_read(ctx)
+        u_nom, u_apply = P.u_nom.clone(), torch.empty(8, device="cuda")
+        lib.mppi_update(ctx, sc.veh, sc.cost, P.solve, P.x_hat, P.x_ref, P.obs, M, u_nom, u_apply)
+        prof = lib.mppi_profile_read(ctx)
+        lib.mppi_profile_enable(ctx, False)
+        dense = P.K * (P.N + 1) * M
+        print(f"M={M}: {prof['obstacle_tests']} tests of {dense} dense")
+        if dense_only:
+            assert prof["obstacle_tests"] == dense
+        else:
+            assert 0 < prof["obstacle_tests"] < 0.5 * dense
+
+
 def test_single_sample_update_is_brute_force(lib, ctx, orc):
     sc = W.c1_plain(K=1, N=12)
     P = DeviceProblem(lib, sc)
