@@ -263,6 +263,8 @@ def calibrate_copy(mib: int, reps: int):
     n = mib * (1 << 20) // 4
     src = torch.rand(n, device="cuda")
     dst = torch.empty_like(src)
+    flush = torch.zeros(128 << 20, device="cuda")     # 512 MiB written after the source
+    flush.add_(1.0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
@@ -489,7 +491,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="oracle CPU-baseline time budget (0 skips it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="only run a device copy of MIB MiB (counter calibration) and exit")
+                    help="only run a device copy of MIB MiB (counter calibration) and exit; "
+                         "use a size well above the 256 MB MALL")
     ap.add_argument("--summarize-rocpd", nargs=2, metavar=("DB", "COMMAND"),
                     help="print a Markdown kernel summary of a rocprofv3 database and exit")
     args = ap.parse_args()
