@@ -65,9 +65,11 @@ def _load():
         "orc_num_threads": (i32, []),
         "orc_weights": (i32, [i32, dp, f64, dp, dp]),
         "orc_weighted_update": (None, [i32, i32, dp, dp, dp]),
-        "orc_apply_shift": (None, [dp, i32, f64, dp, dp, dp, dp]),
+        "orc_advance": (None, [i32, f64, dp, dp]),
+        "orc_apply_shift": (None, [dp, i32, f64, f64, dp, dp, dp, dp]),
+        "orc_predict": (None, [dp, f64, f64, dp, dp, dp]),
         "orc_update": (i32, [dp, dp, i32, i32, f64, f64, dp, u64, u32, u32,
-                             dp, dp, dp, dp, dp, i32, dp, dp, dp, dp, dp]),
+                             dp, f64, dp, dp, dp, dp, i32, dp, dp, dp, dp, dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -290,13 +292,30 @@ def weighted_update(w, du, u_nom):
     return out.reshape(N, 4)
 
 
-def apply_shift(veh, dt, x_hat, u_nom, u_init):
-    """Returns (u_apply [8], shifted u_nom [N, 4])."""
+def apply_shift(veh, dt, x_hat, u_nom, u_init, alpha=1.0):
+    """Returns (u_apply [8], u_nom [N, 4] advanced by alpha of a step; 1 = shift)."""
     un = _d(u_nom).reshape(-1, 4).copy()
     v, xh, ui = vehicle_array(veh), _d(x_hat, NX), _d(u_init, 4)
     ua = np.empty(8)
-    _load().orc_apply_shift(_p(v), un.shape[0], float(dt), _p(xh), _p(ui), _p(un), _p(ua))
+    _load().orc_apply_shift(_p(v), un.shape[0], float(dt), float(alpha), _p(xh), _p(ui),
+                            _p(un), _p(ua))
     return ua, un
+
+
+def advance(u_nom, u_init, alpha):
+    """The warm start advanced by alpha in (0, 1] of a step (Sec. IV-B)."""
+    un = _d(u_nom).reshape(-1, 4).copy()
+    ui = _d(u_init, 4)
+    _load().orc_advance(un.shape[0], float(alpha), _p(ui), _p(un))
+    return un
+
+
+def predict(veh, dt, delay, x, u_hold):
+    """State after `delay` s with u_hold held (Sec. IV-E), steps of at most dt."""
+    v, x, u = vehicle_array(veh), _d(x, NX), _d(u_hold, 4)
+    out = np.empty(NX)
+    _load().orc_predict(_p(v), float(dt), float(delay), _p(x), _p(u), _p(out))
+    return out
 
 
 def update(veh, cost, solve, x_hat, u_nom, x_ref, obs=None):
@@ -312,7 +331,8 @@ def update(veh, cost, solve, x_hat, u_nom, x_ref, obs=None):
     du, S, w = np.empty((K, N, 4)), np.empty(K), np.empty(K)
     rc = _load().orc_update(_p(v), _p(c), K, N, float(solve["dt"]), float(solve["lam"]), _p(s),
                             int(solve["seed"]), int(solve.get("vehicle_id", 0)),
-                            int(solve.get("t", 0)), _p(ui), _p(xh), _p(un), _p(xr), _p(o),
+                            int(solve.get("t", 0)), _p(ui), float(solve.get("dt_ctrl", 0.0)),
+                            _p(xh), _p(un), _p(xr), _p(o),
                             o.shape[0],
                             _p(ua), _p(diag), _p(du), _p(S), _p(w))
     if rc != 0:

@@ -490,27 +490,62 @@ void orc_weighted_update(int K, int N, const double *w, const double *du, double
         }
 }
 
-/* Apply and shift (Algorithm 1, after the update): u_apply[0..3] = u_nom_0,
- * u_apply[4..7] = feasible [F_clip, w_clip] at x_hat; then u_j <- u_{j+1} and
- * u_{N-1} <- u_init (Algorithm 1 takes u_init as an input; hover in the paper). */
-void orc_apply_shift(const double *veh, int N, double dt, const double *x_hat,
+/* Advance of the warm start by a fraction alpha in (0, 1] of a prediction step
+ * (Sec. IV-B, control input interpolation).  The sequence is read as the piecewise-
+ * linear function of the step index through the knots u_0..u_{N-1} and
+ * u_N = u_init (the refill of Algorithm 1); knot j takes that function's value at
+ * j + alpha.  alpha = 1 is Algorithm 1's shift; with the prediction step n times the
+ * time between updates, alpha = 1/n. */
+void orc_advance(int N, double alpha, const double u_init[4], double *u_nom)
+{
+    for (int j = 0; j < N; ++j) {            /* knot j + 1 is still the old value */
+        const double *next = j + 1 < N ? u_nom + (j + 1) * 4 : u_init;
+        for (int d = 0; d < 4; ++d)
+            u_nom[j * 4 + d] = (1.0 - alpha) * u_nom[j * 4 + d] + alpha * next[d];
+    }
+}
+
+/* Apply and advance (Algorithm 1, after the update): u_apply[0..3] = u_nom_0,
+ * u_apply[4..7] = feasible [F_clip, w_clip] at x_hat; then the sequence advances by
+ * alpha of a step (orc_advance; alpha = 1: u_j <- u_{j+1}, u_{N-1} <- u_init, where
+ * Algorithm 1 takes u_init as an input; hover in the paper). */
+void orc_apply_shift(const double *veh, int N, double dt, double alpha, const double *x_hat,
                      const double u_init[4], double *u_nom, double u_apply[8])
 {
     for (int d = 0; d < 4; ++d) u_apply[d] = u_nom[d];
     orc_applied_input(veh, x_hat, u_nom, dt, u_apply + 4);
-    for (int j = 0; j + 1 < N; ++j)
-        for (int d = 0; d < 4; ++d) u_nom[j * 4 + d] = u_nom[(j + 1) * 4 + d];
-    for (int d = 0; d < 4; ++d) u_nom[(N - 1) * 4 + d] = u_init[d];
+    orc_advance(N, alpha, u_init, u_nom);
+}
+
+/* Delay compensation by prediction (Sec. IV-E): the state the vehicle reaches after
+ * `delay` seconds while the previous command u_hold is executed, from the model with
+ * that command held: ceil(delay / dt) equal steps of h <= dt, each the controller of
+ * Eqs. (8)-(12) at the step's start (gain from the prediction step dt) followed by one
+ * RK4 step of length h.  delay = 0 returns x. */
+void orc_predict(const double *veh, double dt, double delay, const double x[ORC_NX],
+                 const double u_hold[4], double x_out[ORC_NX])
+{
+    double cur[ORC_NX], nxt[ORC_NX], T_cmd[4];
+    for (int i = 0; i < ORC_NX; ++i) cur[i] = x[i];
+    int n = delay > 0.0 ? (int)ceil(delay / dt) : 0;
+    double h = n > 0 ? delay / n : 0.0;
+    for (int s = 0; s < n; ++s) {
+        orc_controller(veh, cur, u_hold, dt, T_cmd);
+        orc_rk4_step(veh, cur, T_cmd, h, nxt);
+        for (int i = 0; i < ORC_NX; ++i) cur[i] = nxt[i];
+    }
+    for (int i = 0; i < ORC_NX; ++i) x_out[i] = cur[i];
 }
 
 /* One full iteration of Algorithm 1's loop body for a given state estimate.
- * u_nom [N][4] is updated in place (warm start).  du_out [K][N][4], S_out [K],
+ * u_nom [N][4] is updated in place (warm start); dt_ctrl is the time between updates
+ * (0: one prediction step dt), the warm start advancing by dt_ctrl / dt of a step.  du_out [K][N][4], S_out [K],
  * w_out [K] may be NULL.  Returns 0, or -1 (u_nom untouched) when every
  * rollout cost is non-finite. */
 int orc_update(const double *veh, const double *cost, int K, int N, double dt, double lambda,
                const double sigma[4], uint64_t seed, uint32_t vehicle_id, uint32_t t,
-               const double u_init[4], const double *x_hat, double *u_nom, const double *x_ref,
-               const double *obs, int M, double u_apply[8], double diag[4],
+               const double u_init[4], double dt_ctrl, const double *x_hat, double *u_nom,
+               const double *x_ref, const double *obs, int M, double u_apply[8], double diag[4],
                double *du_out, double *S_out, double *w_out)
 {
     double *du = du_out ? du_out : (double *)malloc(sizeof(double) * (size_t)K * N * 4);
@@ -521,7 +556,8 @@ int orc_update(const double *veh, const double *cost, int K, int N, double dt, d
     int rc = orc_weights(K, S, lambda, w, diag);
     if (rc == 0) {
         orc_weighted_update(K, N, w, du, u_nom);
-        orc_apply_shift(veh, N, dt, x_hat, u_init, u_nom, u_apply);
+        double alpha = dt_ctrl > 0.0 ? dt_ctrl / dt : 1.0;   /* Sec. IV-B */
+        orc_apply_shift(veh, N, dt, alpha, x_hat, u_init, u_nom, u_apply);
     }
     if (!du_out) free(du);
     if (!S_out) free(S);

@@ -535,3 +535,92 @@ def test_rollout_uses_its_own_noise_and_cost(orc):
         for j in range(9):
             x = orc.model_step(sc.veh, x, uk[j], sc.dt)
         np.testing.assert_array_equal(states[k, -1], x)
+
+
+# ---------------------------------------------------------------------------
+# Control input interpolation (Sec. IV-B) and delay compensation (Sec. IV-E)
+# ---------------------------------------------------------------------------
+
+def test_advance_by_a_whole_step_is_the_shift(orc):
+    """alpha = 1 is Algorithm 1's shift: u_j <- u_{j+1}, u_{N-1} <- u_init, exactly."""
+    rng = np.random.default_rng(7)
+    u, ui = rng.normal(size=(9, 4)), rng.normal(size=4)
+    np.testing.assert_array_equal(orc.advance(u, ui, 1.0), np.vstack([u[1:], ui]))
+
+
+@pytest.mark.parametrize("alpha", [0.1, 0.25, 0.5, 0.999])
+def test_advance_is_linear_interpolation(orc, alpha):
+    """Knot j takes the value at j + alpha of the piecewise-linear interpolant through
+    u_0..u_{N-1}, u_N = u_init (numpy.interp per input dimension)."""
+    rng = np.random.default_rng(8)
+    N = 15
+    u, ui = rng.normal(size=(N, 4)), rng.normal(size=4)
+    knots = np.vstack([u, ui])
+    want = np.stack([np.interp(np.arange(N) + alpha, np.arange(N + 1), knots[:, d])
+                     for d in range(4)], axis=1)
+    np.testing.assert_allclose(orc.advance(u, ui, alpha), want, rtol=0, atol=1e-14)
+
+
+def test_advance_of_a_linear_sequence_is_exact(orc):
+    """A sequence linear in j (continued by u_init) moves along its line, and n
+    advances by 1/n equal one whole shift on the knots that the fixed refill u_init
+    has not reached (each advance carries its influence one knot back)."""
+    N, n = 30, 10
+    a, b = np.array([9.0, 0.3, -0.2, 0.1]), np.array([0.5, -0.05, 0.02, 0.01])
+    u = a + b * np.arange(N)[:, None]
+    ui = a + b * N
+    np.testing.assert_allclose(orc.advance(u, ui, 0.3), a + b * (np.arange(N)[:, None] + 0.3),
+                               atol=1e-13)
+    v = u.copy()
+    for _ in range(n):
+        v = orc.advance(v, ui, 1.0 / n)
+    np.testing.assert_allclose(v[:N - n + 1], u[1:N - n + 2], atol=1e-12)
+    assert np.abs(v[-1] - ui).max() > 1e-3          # the refill is approached, not reached
+
+
+def test_update_with_interpolation(orc):
+    """dt_ctrl = dt / 10: the same update, then an advance by 1/10 of a step instead
+    of the shift; u_apply is unchanged."""
+    sc = W.c2_line(K=32, N=15)
+    s = sc.solve(1)
+    un = sc.u_nom0() + np.linspace(0, 1, 15)[:, None] * [0.5, 0.1, -0.1, 0.05]
+    r1 = orc.update(sc.veh, sc.cost, s, sc.x0, un, sc.x_ref(1), sc.obstacles)
+    s2 = dict(s, dt_ctrl=sc.dt / 10)
+    r2 = orc.update(sc.veh, sc.cost, s2, sc.x0, un, sc.x_ref(1), sc.obstacles)
+    np.testing.assert_array_equal(r1["u_apply"], r2["u_apply"])
+    updated = orc.weighted_update(r1["w"], r1["du"], un)
+    np.testing.assert_allclose(r1["u_nom"], np.vstack([updated[1:], sc.u_init]), rtol=1e-15)
+    np.testing.assert_allclose(r2["u_nom"], 0.9 * updated + 0.1 * np.vstack([updated[1:], sc.u_init]),
+                               rtol=1e-14, atol=1e-14)
+
+
+def test_predict_zero_delay_and_one_step(orc):
+    """No delay returns the estimate; a delay of one step dt is one model step."""
+    veh = W.vehicle_benchmark()
+    rng = np.random.default_rng(9)
+    x = hover_state(veh, p=(1.0, 2.0, 3.0))
+    x[3:7] = quat_axis_angle(rng.normal(size=3), 0.4)
+    x[7:13] = rng.normal(size=6)
+    u = np.array([11.0, 0.4, -0.3, 0.2])
+    np.testing.assert_array_equal(orc.predict(veh, 0.01, 0.0, x, u), x)
+    np.testing.assert_array_equal(orc.predict(veh, 0.01, 0.01, x, u), orc.model_step(veh, x, u, 0.01))
+
+
+@pytest.mark.parametrize("tau_m", [0.0, 0.03])
+def test_predict_hover_and_free_fall(orc, tau_m):
+    """Hover is kept over any delay; zero thrust falls as p0 + v0 t - g t^2 / 2 e_z
+    over several sub-steps (exact for RK4), spinning freely about body z with
+    q(t) = q0 (x) exp(Omega t / 2) when J_x = J_y."""
+    veh = W.vehicle_benchmark()
+    veh["tau_m"] = tau_m
+    x = hover_state(veh, p=(0.5, 0.0, 2.0))
+    np.testing.assert_allclose(orc.predict(veh, 0.01, 0.037, x, W.hover_control(veh)), x, atol=1e-13)
+    Om, t = 3.0, 0.025                                   # 3 sub-steps of t / 3
+    x[7:10] = [1.0, -2.0, 0.5]
+    x[10:13] = [0.0, 0.0, Om]
+    x[13:17] = 0.0
+    y = orc.predict(veh, 0.01, t, x, [0.0, 0.0, 0.0, Om])
+    np.testing.assert_allclose(y[0:3], x[0:3] + x[7:10] * t - [0, 0, 0.5 * 9.81 * t * t], atol=1e-13)
+    np.testing.assert_allclose(y[7:10], x[7:10] - [0, 0, 9.81 * t], atol=1e-13)
+    np.testing.assert_allclose(y[3:7], quat_axis_angle([0, 0, 1], Om * t), atol=1e-10)
+    np.testing.assert_allclose(y[10:17], x[10:17], atol=1e-13)
