@@ -7,7 +7,12 @@ every step is one full MPPI update (rollouts, weights, weighted update, apply an
 shift) followed by one noise-free plant step on the device, with the applied control
 copied to the host and the host synchronised per update ("plain": one solve per
 launch sequence).  Inputs (references for every step, obstacles, warm start) are
-resident on the device before the timed region starts.
+resident on the device before the timed region starts.  The same line carries the
+batched leg (256 uneven vehicles per graph replay) and a short served leg (Poisson
+arrivals, each state estimate predicted over the running median latency).
+--config c1 | c3 | paper selects another single-vehicle workload (paper: the paper's
+own Table I/II setting, updates every 10 ms with the interpolated warm start), c4 the
+batched and c5 the full 60 s served workload.
 
 Prints ONE JSON line on stdout (everything else goes to stderr):
   value          rollout-steps/s = K * N * steps / wall time of the timed steps
@@ -82,7 +87,7 @@ def reduction_bytes_per_launch(K: int, N: int) -> float:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("model.h", "kernels.hip", "kernels.h"):
+    for f in ("model.h", "stages.h", "kernels.hip", "kernels.h"):
         with open(os.path.join(ROOT, "paper_2407_09812_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -113,7 +118,7 @@ def cpu_baseline(sc, seconds: float):
     n, t0 = 0, time.perf_counter()
     while True:
         r = oracle.update(sc.veh, sc.cost, sc.solve(n), x, u_nom, sc.x_ref(n), sc.obstacles)
-        x = oracle.model_step(sc.veh, x, r["u_apply"][:4], sc.dt)
+        x = oracle.predict(sc.veh, sc.dt, sc.period, x, r["u_apply"][:4])
         u_nom = r["u_nom"]
         n += 1
         el = time.perf_counter() - t0
@@ -179,7 +184,9 @@ def run(args):
         u_host.copy_(u_apply, non_blocking=True)
         stream.synchronize()
         t1 = time.perf_counter()
-        lib.mppi_plant_step(ctx, sc.veh, sc.dt, xi, u_apply, x_buf[(t + 1) % 2], stream=stream)
+        # plant: one control period with the applied command held
+        lib.mppi_predict(ctx, sc.veh, sc.dt, sc.period, xi, u_apply, x_buf[(t + 1) % 2],
+                         stream=stream)
         if record:
             lat.append((t1 - t0) * 1e3)
 
@@ -226,6 +233,7 @@ def run(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{sc.name}: single vehicle, K={K}, N={N}, dt={sc.dt}, M={M}, "
+                               f"lambda={sc.lam:g}, update period {sc.period} s, "
                                f"closed loop (plain: one solve per launch sequence)",
                    "K": K, "N": N, "M": M, "updates": steps, "rollout_launch": launch},
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99),
@@ -432,7 +440,7 @@ def run_served(args, duration_s: float, rate_hz: float, batch_cfg=None):
         x[13:] = thrust[vid]
         x[:3] += rng.normal(0.0, 0.05, 3).astype(np.float32)
         return srv.submit(vid, K, N, dt, 1.0, (1.0, 1.0, 1.0, 1.0), 5, x, rows[vid][i:i + N + 1],
-                          obs[vid])
+                          obs[vid], delay=args.serve_delay)
 
     for vid in range(8):                          # warm-up: graph capture on every slot
         srv.wait(submit(vid, 1024, 50))
@@ -454,6 +462,7 @@ def run_served(args, duration_s: float, rate_hz: float, batch_cfg=None):
     stats = srv.stats()
     srv.close()
     lat = [1e3 * r["latency_s"] for r in res]
+    delays = [1e3 * r["delay"] for r in res]
     bad = sum(1 for r in res if r["status"] != 0)
     steps = sum(r["K"] * r["N"] for r in res)
     return {
@@ -468,6 +477,9 @@ def run_served(args, duration_s: float, rate_hz: float, batch_cfg=None):
         "max_in_flight": stats["max_in_flight"], "device_busy_frac": stats["busy_s"] / (t_end - t_start),
         "streams": args.serve_streams, "budget_gib": args.serve_budget_gib,
         "submit_lag_s": late,
+        "delay_compensation_ms": {"requested": args.serve_delay * 1e3 if args.serve_delay >= 0
+                                  else "median served latency",
+                                  "mean_used": sum(delays) / len(delays), "max_used": max(delays)},
     }
 
 
@@ -476,13 +488,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "paper"])
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of the served leg beside the plain line (0 skips it); "
                          "--config c5 runs the full 60 s")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-streams", type=int, default=2)
     ap.add_argument("--serve-budget-gib", type=float, default=2.0)
+    ap.add_argument("--serve-delay", type=float, default=-1.0,
+                    help="seconds each served state estimate is predicted forward before its "
+                         "update; < 0: the server's running median latency (default)")
     ap.add_argument("--batched-steps", type=int, default=20,
                     help="batched updates of the 256-vehicle mix timed beside the plain line "
                          "(0 skips the batched leg)")

@@ -14,6 +14,10 @@
  *   6. emits u_nom_0 (and the feasible [F_clip, omega_clip] at x_hat,
  *      Eqs. (12)-(15)), shifts u_nom by one step and refills the last
  *      slot with u_init                                                   Algorithm 1
+ *      -- or, when updates come faster than the prediction step, advances
+ *      u_nom by that fraction of a step by linear interpolation         Sec. IV-B
+ * Upstream of an update, mppi_predict moves the state estimate forward over the
+ * computation delay with the command being executed                      Sec. IV-E
  *
  * Conventions
  *  - Every function returns mppi_status: MPPI_OK (0) or a negative error code.
@@ -111,6 +115,10 @@ typedef struct mppi_solve {
     uint64_t seed;
     uint32_t vehicle_id;
     uint32_t t;
+    float dt_ctrl;     /* time between updates, s, 0 <= dt_ctrl <= dt; 0 means dt.
+                          The warm start advances by alpha = dt_ctrl / dt of a step
+                          (Sec. IV-B); alpha = 1 is Algorithm 1's shift   */
+    uint32_t reserved; /* set to 0                                         */
 } mppi_solve;
 
 /* Diagnostics written by the device (all rollouts of one update). */
@@ -182,12 +190,26 @@ mppi_status mppi_weighted_sum(mppi_ctx *ctx, void *stream, int32_t K, int32_t N,
                               const float *w, const float *du, int32_t ld,
                               const float *u_in, float *u_out, const mppi_diag *diag);
 
-/* Apply and shift (Algorithm 1 after Eq. (5); Eqs. (12)-(15)): u_apply[0..3] =
- * u_upd[0], u_apply[4..7] = [F_clip, omega_clip] at x_hat; u_nom[j] = u_upd[j+1],
- * u_nom[N-1] = solve->u_init.  Device pointers; u_nom may alias u_upd. */
+/* Apply and advance (Algorithm 1 after Eq. (5); Eqs. (12)-(15); Sec. IV-B):
+ * u_apply[0..3] = u_upd[0], u_apply[4..7] = [F_clip, omega_clip] at x_hat; u_nom[j] =
+ * (1 - alpha) u_upd[j] + alpha u_upd[j+1] with u_upd[N] = solve->u_init and
+ * alpha = solve->dt_ctrl / solve->dt (alpha = 1, or dt_ctrl = 0: exactly
+ * u_nom[j] = u_upd[j+1], u_nom[N-1] = u_init).  Device pointers; u_nom must not
+ * alias u_upd (MPPI_E_INVALID_ARG). */
 mppi_status mppi_apply_shift(mppi_ctx *ctx, void *stream, const mppi_vehicle *veh,
                              const mppi_solve *solve, const float *x_hat,
                              const float *u_upd, float *u_nom, float *u_apply);
+
+/* Delay compensation by prediction (Sec. IV-E): x_out = the state reached from x_hat
+ * after `delay` seconds while the command u_hold ([F_t, omega_d], the one being
+ * executed during the computation) is held: ceil(delay / dt) equal steps of length
+ * h <= dt, each the rate controller of Eqs. (8)-(12) at the step's start (gain 1/dt,
+ * or veh->k_rate) followed by one RK4 step of length h.  delay = 0 copies x_hat;
+ * delay = dt is mppi_plant_step.  Device pointers (17, 4, 17 floats); x_out may
+ * alias x_hat.  MPPI_E_INVALID_ARG for dt <= 0, delay < 0 or delay > 4096 dt;
+ * MPPI_E_NONFINITE_INPUT for non-finite dt or delay. */
+mppi_status mppi_predict(mppi_ctx *ctx, void *stream, const mppi_vehicle *veh, float dt,
+                         float delay, const float *x_hat, const float *u_hold, float *x_out);
 
 /* The noise of one update as the rollout kernel draws it: du [N][4][ld] (device). */
 mppi_status mppi_noise(mppi_ctx *ctx, void *stream, const mppi_solve *solve,
@@ -297,7 +319,10 @@ mppi_status mppi_batch_set_config(mppi_ctx *ctx, const mppi_batch_config *cfg);
  * vehicle in flight (the next update starts from the previous result), in arrival
  * order, and launches them as one batch (mppi_batch_update) on the slot's stream;
  * batches on different slots overlap on the device.  A request with horizon N uses
- * the first N rows of its vehicle's warm start and shifts them. */
+ * the first N rows of its vehicle's warm start and advances them.  With a delay, the
+ * request's state estimate is first moved forward by mppi_predict's model steps with
+ * the vehicle's last served command held (u_init before its first request); each
+ * served command is recorded for the vehicle's next request (Sec. IV-E). */
 typedef struct mppi_server mppi_server;
 
 typedef struct mppi_server_cfg {
@@ -318,6 +343,10 @@ typedef struct mppi_server_request {
     int32_t K, N, M;
     float dt, lambda;
     float sigma[4];
+    float dt_ctrl;                 /* as mppi_solve.dt_ctrl (0: shift by a step)   */
+    float delay;                   /* s to predict x_hat forward before the update;
+                                      0: none; < 0: the running median of the last
+                                      256 submit-to-result latencies              */
     uint64_t seed;
     const float *x_hat;            /* host, 17 floats                               */
     const float *x_ref;            /* host, (N+1) x 13 floats                       */
@@ -332,6 +361,8 @@ typedef struct mppi_server_result {
     mppi_diag diag;
     double submit_s, launch_s, done_s;   /* server clock, seconds since creation    */
     int32_t K, N;
+    float delay;                   /* delay the state estimate was predicted over  */
+    int32_t reserved;
 } mppi_server_result;
 
 typedef struct mppi_server_stats {
@@ -358,7 +389,8 @@ mppi_status mppi_server_wait(mppi_server *srv, uint64_t ticket, mppi_server_resu
 mppi_status mppi_server_drain(mppi_server *srv);
 mppi_status mppi_server_stats_get(mppi_server *srv, mppi_server_stats *out);
 double mppi_server_clock(const mppi_server *srv);
-/* Warm starts and update counters: size = n_vehicles (N_max x 4 floats + 1 uint32).
+/* Warm starts, last served commands and update counters: size = n_vehicles x
+ * (N_max x 4 + 4 floats) + n_vehicles uint32.
  * Both drain first; restore makes the next updates continue exactly (counter-based
  * noise). */
 mppi_status mppi_server_snapshot(mppi_server *srv, void *host_buf, size_t *size);
@@ -376,7 +408,7 @@ typedef struct mppi_profile {
     int64_t batches;
     double batch_rollout_ms, batch_rest_ms;
     int64_t obstacle_tests;   /* sample-state-obstacle distance tests performed (both paths);
-                                 obstacles out of a wave's reach are skipped, see DESIGN */
+                                 obstacles out of every lane's reach in a wave are skipped */
 } mppi_profile;
 
 mppi_status mppi_profile_enable(mppi_ctx *ctx, int32_t on);

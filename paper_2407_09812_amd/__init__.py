@@ -55,7 +55,8 @@ class Cost(C.Structure):
 class Solve(C.Structure):
     _fields_ = [("K", C.c_int32), ("N", C.c_int32), ("dt", C.c_float), ("lam", C.c_float),
                 ("sigma", C.c_float * 4), ("u_init", C.c_float * 4), ("seed", C.c_uint64),
-                ("vehicle_id", C.c_uint32), ("t", C.c_uint32)]
+                ("vehicle_id", C.c_uint32), ("t", C.c_uint32), ("dt_ctrl", C.c_float),
+                ("reserved", C.c_uint32)]
 
 
 class Diag(C.Structure):
@@ -89,6 +90,7 @@ class ServerCfg(C.Structure):
 class ServerRequest(C.Structure):
     _fields_ = [("vehicle_id", C.c_uint32), ("K", C.c_int32), ("N", C.c_int32), ("M", C.c_int32),
                 ("dt", C.c_float), ("lam", C.c_float), ("sigma", C.c_float * 4),
+                ("dt_ctrl", C.c_float), ("delay", C.c_float),
                 ("seed", C.c_uint64), ("x_hat", C.c_void_p), ("x_ref", C.c_void_p),
                 ("obs", C.c_void_p)]
 
@@ -97,7 +99,7 @@ class ServerResult(C.Structure):
     _fields_ = [("ticket", C.c_uint64), ("vehicle_id", C.c_uint32), ("t", C.c_uint32),
                 ("u_apply", C.c_float * 8), ("diag", Diag), ("submit_s", C.c_double),
                 ("launch_s", C.c_double), ("done_s", C.c_double), ("K", C.c_int32),
-                ("N", C.c_int32)]
+                ("N", C.c_int32), ("delay", C.c_float), ("reserved", C.c_int32)]
 
 
 class ServerStats(C.Structure):
@@ -138,6 +140,7 @@ _SIGS = {
     "mppi_noise": [_vp, _vp, _PS, _vp, _i32],
     "mppi_philox": [_vp, _vp, _i32, _vp, _vp, _vp],
     "mppi_plant_step": [_vp, _vp, _PV, _f32, _vp, _vp, _vp],
+    "mppi_predict": [_vp, _vp, _PV, _f32, _f32, _vp, _vp, _vp],
     "mppi_get_config": [_vp, _i32, _i32, _i32, C.POINTER(LaunchConfig)],
     "mppi_set_config": [_vp, _i32, _i32, _i32, C.POINTER(LaunchConfig)],
     "mppi_autotune": [_vp, _vp, _PV, _PC, _PS, _vp, _vp, _vp, _i32, _vp, _i32,
@@ -204,6 +207,7 @@ def solve(d: dict) -> Solve:
     s.seed = int(d["seed"]) & 0xFFFFFFFFFFFFFFFF
     s.vehicle_id = int(d.get("vehicle_id", 0)) & 0xFFFFFFFF
     s.t = int(d.get("t", 0)) & 0xFFFFFFFF
+    s.dt_ctrl = float(d.get("dt_ctrl", 0.0))
     return s
 
 
@@ -345,6 +349,12 @@ def mppi_plant_step(ctx, veh, dt, x, u, x_out, stream=None):
                                    _ptr(u), _ptr(x_out)), "mppi_plant_step")
 
 
+def mppi_predict(ctx, veh, dt, delay, x_hat, u_hold, x_out, stream=None):
+    v = vehicle(veh)
+    ctx.check(_lib.mppi_predict(ctx.handle, _stream(stream), C.byref(v), float(dt), float(delay),
+                                _ptr(x_hat), _ptr(u_hold), _ptr(x_out)), "mppi_predict")
+
+
 def mppi_get_config(ctx, K, N, M) -> dict:
     c = LaunchConfig()
     ctx.check(_lib.mppi_get_config(ctx.handle, int(K), int(N), int(M), C.byref(c)), "mppi_get_config")
@@ -436,7 +446,7 @@ def _result_dict(r: ServerResult) -> dict:
                 status=r.diag.status, rho=r.diag.rho, ess=r.diag.ess, argmin=r.diag.argmin,
                 lanes=r.diag.lanes,
                 submit_s=r.submit_s, launch_s=r.launch_s, done_s=r.done_s, K=r.K, N=r.N,
-                latency_s=r.done_s - r.submit_s)
+                delay=r.delay, latency_s=r.done_s - r.submit_s)
 
 
 class Server:
@@ -464,11 +474,15 @@ class Server:
         self._check(_lib.mppi_server_set_batch_config(self.handle, C.byref(c)),
                     "mppi_server_set_batch_config")
 
-    def submit(self, vehicle_id, K, N, dt, lam, sigma, seed, x_hat, x_ref, obs=None) -> int:
-        """x_hat [17], x_ref [(N+1), 13] host arrays; obs an OBSTACLE_DTYPE array."""
+    def submit(self, vehicle_id, K, N, dt, lam, sigma, seed, x_hat, x_ref, obs=None,
+               dt_ctrl=0.0, delay=0.0) -> int:
+        """x_hat [17], x_ref [(N+1), 13] host arrays; obs an OBSTACLE_DTYPE array;
+        dt_ctrl the time between updates (0: dt); delay the seconds to predict x_hat
+        forward (< 0: the server's median latency)."""
         r = ServerRequest()
         r.vehicle_id, r.K, r.N = int(vehicle_id), int(K), int(N)
         r.dt, r.lam = float(dt), float(lam)
+        r.dt_ctrl, r.delay = float(dt_ctrl), float(delay)
         r.sigma = (C.c_float * 4)(*[float(v) for v in sigma])
         r.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
         xh = np.ascontiguousarray(x_hat, dtype=np.float32)

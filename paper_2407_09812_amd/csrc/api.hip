@@ -67,10 +67,17 @@ mppi_status check_solve(const mppi_solve* s)
     const float vals[10] = {s->dt, s->lambda, s->sigma[0], s->sigma[1], s->sigma[2], s->sigma[3],
                             s->u_init[0], s->u_init[1], s->u_init[2], s->u_init[3]};
     if (!finite_all(vals, 10)) return MPPI_E_NONFINITE_INPUT;
+    if (!std::isfinite(s->dt_ctrl)) return MPPI_E_NONFINITE_INPUT;
     if (!(s->dt > 0) || !(s->lambda > 0)) return MPPI_E_INVALID_ARG;
+    if (s->dt_ctrl < 0 || s->dt_ctrl > s->dt) return MPPI_E_INVALID_ARG;
     for (int d = 0; d < 4; ++d)
         if (s->sigma[d] < 0) return MPPI_E_INVALID_ARG;
     return MPPI_OK;
+}
+
+float advance_fraction(const mppi_solve& s)
+{
+    return s.dt_ctrl > 0 ? (float)((double)s.dt_ctrl / (double)s.dt) : 1.0f;
 }
 
 ModelParams model_params(const mppi_vehicle& v, float dt)
@@ -104,6 +111,22 @@ ModelParams model_params(const mppi_vehicle& v, float dt)
     P.dt = dt;
     P.w_xy_max = v.w_xy_max;
     P.w_z_max = v.w_z_max;
+    return P;
+}
+
+int predict_steps(float dt, float delay)
+{
+    if (!(dt > 0) || !(delay >= 0)) return -1;
+    const double n = std::ceil((double)delay / (double)dt);
+    return n <= kPredictMaxSteps ? (int)n : -1;
+}
+
+ModelParams predict_params(const mppi_vehicle& v, float dt, float delay, int steps)
+{
+    // Steps of h = delay / steps; the rate controller's gain stays that of the
+    // prediction step dt (Eq. (8)).
+    ModelParams P = model_params(v, steps > 0 ? (float)((double)delay / steps) : dt);
+    P.k_w = v.k_rate > 0.0f ? v.k_rate : (float)(1.0 / dt);
     return P;
 }
 
@@ -334,7 +357,7 @@ mppi_status mppi_update(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh, co
                                      ctx->u_upd, dg, s));
     HIP_TRY(ctx, mark(3));
     HIP_TRY(ctx, launch_apply_shift(a.mp, x_hat, ctx->u_upd, u_nom, u_apply, solve->N,
-                                    solve->u_init, dg, s));
+                                    solve->u_init, advance_fraction(*solve), dg, s));
     HIP_TRY(ctx, mark(4));
     if (ctx->profiling)
         for (int i = 0; i < kEventsPerUpdate; ++i) ctx->pending.push_back(ev[i]);
@@ -458,7 +481,8 @@ mppi_status mppi_apply_shift(mppi_ctx* ctx, void* stream, const mppi_vehicle* ve
     if (!x_hat || !u_upd || !u_nom || !u_apply || u_upd == u_nom)
         return fail(ctx, MPPI_E_INVALID_ARG, "apply_shift: null or aliased pointer");
     HIP_TRY(ctx, launch_apply_shift(model_params(*veh, solve->dt), x_hat, u_upd, u_nom, u_apply,
-                                    solve->N, solve->u_init, nullptr, (hipStream_t)stream));
+                                    solve->N, solve->u_init, advance_fraction(*solve), nullptr,
+                                    (hipStream_t)stream));
     return MPPI_OK;
 }
 
@@ -494,7 +518,23 @@ mppi_status mppi_plant_step(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh
     if (st != MPPI_OK) return fail(ctx, st, "plant_step: invalid vehicle");
     if (!std::isfinite(dt) || !(dt > 0) || !x || !u || !x_out)
         return fail(ctx, MPPI_E_INVALID_ARG, "plant_step: bad argument");
-    HIP_TRY(ctx, launch_plant(model_params(*veh, dt), x, u, x_out, (hipStream_t)stream));
+    HIP_TRY(ctx, launch_plant(model_params(*veh, dt), x, u, x_out, 1, (hipStream_t)stream));
+    return MPPI_OK;
+}
+
+mppi_status mppi_predict(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh, float dt,
+                         float delay, const float* x_hat, const float* u_hold, float* x_out)
+{
+    if (!ctx) return MPPI_E_INVALID_ARG;
+    mppi_status st = check_vehicle(veh);
+    if (st != MPPI_OK) return fail(ctx, st, "predict: invalid vehicle");
+    if (!std::isfinite(dt) || !std::isfinite(delay))
+        return fail(ctx, MPPI_E_NONFINITE_INPUT, "predict: non-finite dt or delay");
+    const int steps = predict_steps(dt, delay);
+    if (!(dt > 0) || steps < 0 || !x_hat || !u_hold || !x_out)
+        return fail(ctx, MPPI_E_INVALID_ARG, "predict: bad argument");
+    HIP_TRY(ctx, launch_plant(predict_params(*veh, dt, delay, steps), x_hat, u_hold, x_out, steps,
+                              (hipStream_t)stream));
     return MPPI_OK;
 }
 

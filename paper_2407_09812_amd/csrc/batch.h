@@ -14,6 +14,7 @@ namespace mppi {
 struct InstanceDesc {
     RolloutParams rp;            // model, cost, noise, M, K, N, ld
     float lambda;
+    float alpha;                 // warm-start advance per update, (0, 1]
     float u_init[4];
     int row0;                    // first weighted-sum row of this instance (4 N rows)
     int lanes;                   // lanes per sample (1, 2, 4, 8)

@@ -96,7 +96,8 @@ __global__ void batch_apply_kernel(const BatchHeader* __restrict__ hdr,
     if (i >= hdr->n_inst) return;
     const InstanceDesc& D = descs[i];
     apply_shift_block(D.rp.mp, D.x_hat, D.u_upd, D.u_nom, D.u_apply, D.rp.N,
-                      make_float4(D.u_init[0], D.u_init[1], D.u_init[2], D.u_init[3]), D.diag);
+                      make_float4(D.u_init[0], D.u_init[1], D.u_init[2], D.u_init[3]), D.alpha,
+                      D.diag);
 }
 
 // ---------------------------------------------------------------------------

@@ -104,6 +104,7 @@ size_t fill_plan(mppi_ctx* ctx, const mppi_request* reqs, int n, const BatchLaun
         D.rp.M = q.M; D.rp.K = K; D.rp.N = N; D.rp.ld = ld;
         D.rp.obs_tests = ctx->profiling ? ctx->obs_tests : nullptr;
         D.lambda = q.solve.lambda;
+        D.alpha = advance_fraction(q.solve);
         for (int d = 0; d < 4; ++d) D.u_init[d] = q.solve.u_init[d];
         D.row0 = row;
         int lanes = cfg.lanes;

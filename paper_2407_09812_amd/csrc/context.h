@@ -66,6 +66,13 @@ mppi_status check_cost(const mppi_cost* c);
 mppi_status check_solve(const mppi_solve* s);
 ModelParams model_params(const mppi_vehicle& v, float dt);
 CostParams cost_params(const mppi_cost& c);
+// Fraction of a prediction step the warm start advances per update (Sec. IV-B).
+float advance_fraction(const mppi_solve& s);
+// Delay prediction (Sec. IV-E): number of equal steps of at most dt covering delay
+// (-1 if invalid or above kPredictMaxSteps), and the model parameters of those steps.
+constexpr int kPredictMaxSteps = 4096;
+int predict_steps(float dt, float delay);
+ModelParams predict_params(const mppi_vehicle& v, float dt, float delay, int steps);
 NoiseParams noise_params(const mppi_solve& s);
 void free_batch(mppi_ctx* ctx);
 mppi_status batch_reserve_raw(mppi_ctx* ctx, int n, size_t du, size_t k, size_t u, size_t items,

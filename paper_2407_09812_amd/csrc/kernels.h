@@ -46,9 +46,9 @@ hipError_t launch_weighted_sum(const float* w, const float* du, int K, int N, in
                                hipStream_t stream);
 hipError_t launch_apply_shift(const ModelParams& P, const float* x_hat, const float* u_upd,
                               float* u_nom, float* u_apply, int N, const float u_init[4],
-                              const mppi_diag* diag, hipStream_t stream);
+                              float alpha, const mppi_diag* diag, hipStream_t stream);
 hipError_t launch_plant(const ModelParams& P, const float* x, const float* u, float* x_out,
-                        hipStream_t stream);
+                        int steps, hipStream_t stream);
 hipError_t launch_noise(const NoiseParams& np, int K, int N, float* du, int ld, hipStream_t stream);
 hipError_t launch_philox(int n, const uint32_t* ctr, const uint32_t* key, uint32_t* out,
                          hipStream_t stream);

@@ -7,8 +7,8 @@
 //                       sum of exp(-(S - rho)/lambda), normalisation   Eq. (4)
 //   weighted_sum_kernel one workgroup per (j, d) row of delta_u [N][4][ld]:
 //                       coalesced float4 GEMV against the weights       Eq. (5)
-//   apply_shift_kernel  u_apply and the shifted warm start              Algorithm 1
-//   plant_kernel        one noise-free model step (closed-loop plant)
+//   apply_shift_kernel  u_apply and the advanced warm start   Algorithm 1, Sec. IV-B
+//   plant_kernel        noise-free model steps (plant, delay prediction)  Sec. IV-E
 //   noise_kernel, philox_kernel   the rollout's noise on its own (checks)
 #include <hip/hip_runtime.h>
 
@@ -49,35 +49,19 @@ __global__ __launch_bounds__(kSumThreads) void weighted_sum_kernel(
 __global__ void apply_shift_kernel(ModelParams P, const float* __restrict__ x_hat,
                                    const float* __restrict__ u_upd, float* __restrict__ u_nom,
                                    float* __restrict__ u_apply, int N, float4 u_init,
-                                   const mppi_diag* __restrict__ diag)
+                                   float alpha, const mppi_diag* __restrict__ diag)
 {
-    apply_shift_block(P, x_hat, u_upd, u_nom, u_apply, N, u_init, diag);
+    apply_shift_block(P, x_hat, u_upd, u_nom, u_apply, N, u_init, alpha, diag);
 }
 
 // ---------------------------------------------------------------------------
 // Plant, noise and Philox kernels
 // ---------------------------------------------------------------------------
 
-__global__ void plant_kernel(ModelParams P, const float* __restrict__ x_in,
-                             const float* __restrict__ u_in, float* __restrict__ x_out)
+__global__ void plant_kernel(ModelParams P, const float* x_in, const float* __restrict__ u_in,
+                             float* x_out, int steps)
 {
-    if (threadIdx.x != 0) return;
-    State x;
-    x.px = x_in[0]; x.py = x_in[1]; x.pz = x_in[2];
-    x.qw = x_in[3]; x.qx = x_in[4]; x.qy = x_in[5]; x.qz = x_in[6];
-    x.vx = x_in[7]; x.vy = x_in[8]; x.vz = x_in[9];
-    x.wx = x_in[10]; x.wy = x_in[11]; x.wz = x_in[12];
-    x.T0 = x_in[13]; x.T1 = x_in[14]; x.T2 = x_in[15]; x.T3 = x_in[16];
-    const float u[4] = {u_in[0], u_in[1], u_in[2], u_in[3]};
-    float Tc[4];
-    rate_controller(P, x.wx, x.wy, x.wz, u, Tc);
-    if (P.lag)
-        rk4_step<true>(P, x, Tc);
-    else
-        rk4_step<false>(P, x, Tc);
-    const float out[17] = {x.px, x.py, x.pz, x.qw, x.qx, x.qy, x.qz, x.vx, x.vy, x.vz,
-                           x.wx, x.wy, x.wz, x.T0, x.T1, x.T2, x.T3};
-    for (int i = 0; i < 17; ++i) x_out[i] = out[i];
+    if (threadIdx.x == 0) model_steps(P, x_in, u_in, x_out, steps);
 }
 
 __global__ void noise_kernel(NoiseParams np, int K, int N, float* __restrict__ du, int ld)
@@ -161,18 +145,18 @@ hipError_t launch_weighted_sum(const float* w, const float* du, int K, int N, in
 
 hipError_t launch_apply_shift(const ModelParams& P, const float* x_hat, const float* u_upd,
                               float* u_nom, float* u_apply, int N, const float u_init[4],
-                              const mppi_diag* diag, hipStream_t stream)
+                              float alpha, const mppi_diag* diag, hipStream_t stream)
 {
     const float4 ui = make_float4(u_init[0], u_init[1], u_init[2], u_init[3]);
     hipLaunchKernelGGL(apply_shift_kernel, dim3(1), dim3(256), 0, stream, P, x_hat, u_upd, u_nom,
-                       u_apply, N, ui, diag);
+                       u_apply, N, ui, alpha, diag);
     return hipGetLastError();
 }
 
 hipError_t launch_plant(const ModelParams& P, const float* x, const float* u, float* x_out,
-                        hipStream_t stream)
+                        int steps, hipStream_t stream)
 {
-    hipLaunchKernelGGL(plant_kernel, dim3(1), dim3(64), 0, stream, P, x, u, x_out);
+    hipLaunchKernelGGL(plant_kernel, dim3(1), dim3(64), 0, stream, P, x, u, x_out, steps);
     return hipGetLastError();
 }
 

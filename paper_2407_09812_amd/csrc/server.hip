@@ -8,6 +8,11 @@
 // pinned memory and launches them as one batched update; results come back to pinned
 // memory behind an event that the worker polls.  Slots run concurrently, so requests
 // that arrive while a batch runs are admitted into the next free slot.
+//
+// Delay compensation (Sec. IV-E): before a batch runs, each request's state estimate
+// can be moved forward over its delay (given, or the running median of the served
+// latency) with its vehicle's last served command held, by the same model steps as
+// mppi_predict; after the batch, each vehicle's served command is recorded.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,6 +29,7 @@
 #include <vector>
 
 #include "context.h"
+#include "stages.h"
 
 using namespace mppi;
 
@@ -38,7 +44,7 @@ struct Pending {
     uint64_t ticket;
     uint32_t vid;
     int K, N, M;
-    float dt, lambda, sigma[4];
+    float dt, lambda, sigma[4], dt_ctrl, delay;
     uint64_t seed;
     std::vector<float> x_hat, x_ref;
     std::vector<mppi_obstacle> obs;
@@ -54,6 +60,30 @@ struct Footprint {
     }
 };
 
+// Per request, on the device: the delay prediction of its state estimate and the
+// record of its vehicle's served command.
+struct ServeItem {
+    ModelParams P;          // steps of the prediction
+    float* x;               // the request's state estimate, predicted in place
+    float* hold;            // the vehicle's last served command (4 floats)
+    const float* u_apply;   // this request's command
+    int steps;              // 0: no prediction
+};
+
+__global__ void serve_predict_kernel(const ServeItem* __restrict__ items, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && items[i].steps > 0)
+        model_steps(items[i].P, items[i].x, items[i].hold, items[i].x, items[i].steps);
+}
+
+__global__ void serve_record_kernel(const ServeItem* __restrict__ items, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        for (int d = 0; d < 4; ++d) items[i].hold[d] = items[i].u_apply[d];
+}
+
 Footprint footprint(int K, int N, int M)
 {
     Footprint f;
@@ -62,11 +92,12 @@ Footprint footprint(int K, int N, int M)
     f.u = 4 * (size_t)N;
     f.items = (size_t)(K + 7) / 8;
     f.in_bytes = align16(sizeof(float) * 17) + align16(sizeof(float) * 13 * (size_t)(N + 1)) +
-                 align16(sizeof(mppi_obstacle) * (size_t)M);
+                 align16(sizeof(mppi_obstacle) * (size_t)M) + align16(sizeof(ServeItem));
     return f;
 }
 
 constexpr int kOutFloats = 16;   // per request: u_apply (8 floats) + mppi_diag (32 bytes)
+constexpr size_t kLatencyWindow = 256;
 
 struct Slot {
     mppi_ctx* ctx = nullptr;
@@ -80,6 +111,7 @@ struct Slot {
     bool busy = false;
     std::vector<Pending> batch;
     std::vector<uint32_t> ts;
+    std::vector<float> delays;
     std::vector<mppi_request> reqs;
     double launch_s = 0.0;
 };
@@ -89,8 +121,11 @@ struct Slot {
 struct mppi_server {
     mppi_server_cfg cfg{};
     Clock::time_point t0;
-    float* u_warm = nullptr;                   // device [n_vehicles][N_max][4]
+    float* u_warm = nullptr;                   // device [n_vehicles][N_max][4], then
+    float* u_hold = nullptr;                   //   [n_vehicles][4] last served commands
     std::vector<uint32_t> t_next;
+    std::vector<double> latency;               // submit-to-result seconds, ring
+    size_t latency_next = 0;
     std::vector<char> in_flight, seen;
     std::deque<Pending> queue;
     std::unordered_map<uint64_t, mppi_server_result> results;
@@ -108,6 +143,7 @@ struct mppi_server {
     bool bcfg_dirty = false;
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+    size_t warm_floats() const { return (size_t)cfg.n_vehicles * (cfg.N_max * 4 + 4); }
 };
 
 namespace {
@@ -130,6 +166,7 @@ void fail_batch(mppi_server* s, Slot& sl, int32_t status)
         for (float& v : r.u_apply) v = NAN;
         r.diag.status = status;
         r.submit_s = p.submit_s; r.launch_s = sl.launch_s; r.done_s = now; r.K = p.K; r.N = p.N;
+        r.delay = i < sl.delays.size() ? sl.delays[i] : 0.0f;
         s->results[p.ticket] = r;
         s->in_flight[p.vid] = 0;
         s->stats.completed += 1;
@@ -156,7 +193,14 @@ void harvest(mppi_server* s, Slot& sl)
         r.done_s = now;
         r.K = p.K;
         r.N = p.N;
+        r.delay = sl.delays[i];
         s->results[p.ticket] = r;
+        if (s->latency.size() < kLatencyWindow) {
+            s->latency.push_back(now - p.submit_s);
+        } else {
+            s->latency[s->latency_next] = now - p.submit_s;
+            s->latency_next = (s->latency_next + 1) % kLatencyWindow;
+        }
         s->in_flight[p.vid] = 0;
         s->stats.completed += 1;
         s->stats.rollout_steps += (int64_t)p.K * p.N;
@@ -167,6 +211,15 @@ void harvest(mppi_server* s, Slot& sl)
     sl.busy = false;
     if (--s->busy_slots == 0) s->stats.busy_s += now - s->busy_since;
     s->cv_done.notify_all();
+}
+
+// Median submit-to-result latency of the last completed requests (0 before any).
+double latency_estimate(mppi_server* s)
+{
+    if (s->latency.empty()) return 0.0;
+    std::vector<double> v(s->latency);
+    std::nth_element(v.begin(), v.begin() + v.size() / 2, v.end());
+    return v[v.size() / 2];
 }
 
 // Admit queued requests into a free slot and launch them.  Called with the lock held.
@@ -196,12 +249,16 @@ bool dispatch(mppi_server* s, Slot& sl)
     const int n = (int)sl.batch.size();
     sl.reqs.assign(n, mppi_request{});
     sl.ts.assign(n, 0);
+    sl.delays.assign(n, 0.0f);
+    std::vector<size_t> o_x(n);
+    bool predict = false;
+    double auto_delay = -1.0;
     size_t off = 0;
     for (int i = 0; i < n; ++i) {
         const Pending& p = sl.batch[i];
         float* xh = reinterpret_cast<float*>(sl.in_host + off);
         std::memcpy(xh, p.x_hat.data(), sizeof(float) * 17);
-        const size_t o_xh = off;
+        const size_t o_xh = o_x[i] = off;
         off += align16(sizeof(float) * 17);
         std::memcpy(sl.in_host + off, p.x_ref.data(), sizeof(float) * p.x_ref.size());
         const size_t o_xr = off;
@@ -216,6 +273,7 @@ bool dispatch(mppi_server* s, Slot& sl)
         r.solve.K = p.K; r.solve.N = p.N; r.solve.dt = p.dt; r.solve.lambda = p.lambda;
         for (int d = 0; d < 4; ++d) { r.solve.sigma[d] = p.sigma[d]; r.solve.u_init[d] = s->cfg.u_init[d]; }
         r.solve.seed = p.seed;
+        r.solve.dt_ctrl = p.dt_ctrl;
         r.solve.vehicle_id = p.vid;
         r.solve.t = sl.ts[i] = s->t_next[p.vid]++;
         r.x_hat = reinterpret_cast<const float*>(sl.in_dev + o_xh);
@@ -226,14 +284,44 @@ bool dispatch(mppi_server* s, Slot& sl)
         r.u_apply = sl.out_dev + kOutFloats * i;
         r.diag = reinterpret_cast<mppi_diag*>(sl.out_dev + kOutFloats * i + 8);
         s->in_flight[p.vid] = 1;
+        float delay = p.delay;
+        if (delay < 0) {
+            if (auto_delay < 0) auto_delay = latency_estimate(s);
+            delay = (float)std::min(auto_delay, (double)kPredictMaxSteps * p.dt);
+        }
+        sl.delays[i] = delay;
+        predict = predict || delay > 0;
     }
+    // the per-request items follow the inputs
+    const size_t o_items = off;
+    ServeItem* items = reinterpret_cast<ServeItem*>(sl.in_host + o_items);
+    for (int i = 0; i < n; ++i) {
+        const Pending& p = sl.batch[i];
+        ServeItem& it = items[i];
+        it.steps = std::max(predict_steps(p.dt, sl.delays[i]), 0);
+        it.P = predict_params(s->cfg.veh, p.dt, sl.delays[i], it.steps);
+        it.x = reinterpret_cast<float*>(sl.in_dev + o_x[i]);
+        it.hold = s->u_hold + 4 * (size_t)p.vid;
+        it.u_apply = sl.out_dev + kOutFloats * i;
+    }
+    off += sizeof(ServeItem) * n;
+    const ServeItem* items_dev = reinterpret_cast<const ServeItem*>(sl.in_dev + o_items);
+    const int grid = (n + 63) / 64;
     sl.launch_s = s->now();
     s->in_flight_reqs += n;
     s->stats.max_in_flight = std::max(s->stats.max_in_flight, s->in_flight_reqs);
     hipError_t e = hipMemcpyAsync(sl.in_dev, sl.in_host, off, hipMemcpyHostToDevice, sl.stream);
+    if (e == hipSuccess && predict) {
+        hipLaunchKernelGGL(serve_predict_kernel, dim3(grid), dim3(64), 0, sl.stream, items_dev, n);
+        e = hipGetLastError();
+    }
     mppi_status st = e == hipSuccess ? mppi_batch_update(sl.ctx, sl.stream, sl.reqs.data(), n)
                                      : MPPI_E_HIP;
-    if (st == MPPI_OK)
+    if (st == MPPI_OK) {
+        hipLaunchKernelGGL(serve_record_kernel, dim3(grid), dim3(64), 0, sl.stream, items_dev, n);
+        e = hipGetLastError();
+    }
+    if (st == MPPI_OK && e == hipSuccess)
         e = hipMemcpyAsync(sl.out_host, sl.out_dev, sizeof(float) * kOutFloats * n,
                            hipMemcpyDeviceToHost, sl.stream);
     if (st == MPPI_OK && e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
@@ -333,9 +421,10 @@ mppi_status mppi_server_create(const mppi_server_cfg* cfg, mppi_server** out)
     s->in_flight.assign(cfg->n_vehicles, 0);
     s->seen.assign(cfg->n_vehicles, 0);
     bool ok = hipSetDevice(cfg->device) == hipSuccess;
-    const size_t warm = (size_t)cfg->n_vehicles * cfg->N_max * 4;
+    const size_t warm = s->warm_floats();
     if (ok) ok = hipMalloc(&s->u_warm, sizeof(float) * warm) == hipSuccess;
     if (ok) {
+        s->u_hold = s->u_warm + (size_t)cfg->n_vehicles * cfg->N_max * 4;
         std::vector<float> init(warm);
         for (size_t i = 0; i < warm; ++i) init[i] = cfg->u_init[i & 3];
         ok = hipMemcpy(s->u_warm, init.data(), sizeof(float) * warm, hipMemcpyHostToDevice) == hipSuccess;
@@ -416,6 +505,9 @@ mppi_status mppi_server_submit(mppi_server* s, const mppi_server_request* r, uin
         return MPPI_E_INVALID_ARG;
     if (!std::isfinite(r->dt) || !(r->dt > 0) || !std::isfinite(r->lambda) || !(r->lambda > 0))
         return MPPI_E_INVALID_ARG;
+    if (!std::isfinite(r->dt_ctrl) || r->dt_ctrl < 0 || r->dt_ctrl > r->dt || !std::isfinite(r->delay) ||
+        (r->delay >= 0 && predict_steps(r->dt, r->delay) < 0))
+        return MPPI_E_INVALID_ARG;
     for (float sg : r->sigma)
         if (!std::isfinite(sg) || sg < 0) return MPPI_E_INVALID_ARG;
     const Footprint f = footprint(r->K, r->N, r->M);
@@ -426,6 +518,7 @@ mppi_status mppi_server_submit(mppi_server* s, const mppi_server_request* r, uin
     }
     Pending p;
     p.vid = r->vehicle_id; p.K = r->K; p.N = r->N; p.M = r->M; p.dt = r->dt; p.lambda = r->lambda;
+    p.dt_ctrl = r->dt_ctrl; p.delay = r->delay;
     for (int d = 0; d < 4; ++d) p.sigma[d] = r->sigma[d];
     p.seed = r->seed;
     p.x_hat.assign(r->x_hat, r->x_hat + 17);
@@ -492,7 +585,7 @@ double mppi_server_clock(const mppi_server* s)
 mppi_status mppi_server_snapshot(mppi_server* s, void* buf, size_t* size)
 {
     if (!s || !size) return MPPI_E_INVALID_ARG;
-    const size_t warm = sizeof(float) * (size_t)s->cfg.n_vehicles * s->cfg.N_max * 4;
+    const size_t warm = sizeof(float) * s->warm_floats();
     const size_t need = warm + sizeof(uint32_t) * s->cfg.n_vehicles;
     if (!buf) { *size = need; return MPPI_OK; }
     if (*size < need) { *size = need; return MPPI_E_INVALID_ARG; }
@@ -508,7 +601,7 @@ mppi_status mppi_server_snapshot(mppi_server* s, void* buf, size_t* size)
 mppi_status mppi_server_restore(mppi_server* s, const void* buf, size_t size)
 {
     if (!s || !buf) return MPPI_E_INVALID_ARG;
-    const size_t warm = sizeof(float) * (size_t)s->cfg.n_vehicles * s->cfg.N_max * 4;
+    const size_t warm = sizeof(float) * s->warm_floats();
     if (size != warm + sizeof(uint32_t) * s->cfg.n_vehicles) return MPPI_E_INVALID_ARG;
     mppi_status st = mppi_server_drain(s);
     if (st != MPPI_OK) return st;

@@ -336,12 +336,37 @@ __device__ __forceinline__ void feasible_input(const ModelParams& P, const float
     }
 }
 
+// `steps` noise-free model steps of one command held (the closed-loop plant, and the
+// delay prediction of Sec. IV-E), by one thread; x_out may alias x_in.
+__device__ inline void model_steps(const ModelParams& P, const float* x_in,
+                                   const float* __restrict__ u_in, float* x_out, int steps)
+{
+    State x;
+    x.px = x_in[0]; x.py = x_in[1]; x.pz = x_in[2];
+    x.qw = x_in[3]; x.qx = x_in[4]; x.qy = x_in[5]; x.qz = x_in[6];
+    x.vx = x_in[7]; x.vy = x_in[8]; x.vz = x_in[9];
+    x.wx = x_in[10]; x.wy = x_in[11]; x.wz = x_in[12];
+    x.T0 = x_in[13]; x.T1 = x_in[14]; x.T2 = x_in[15]; x.T3 = x_in[16];
+    const float u[4] = {u_in[0], u_in[1], u_in[2], u_in[3]};
+    for (int s = 0; s < steps; ++s) {
+        float Tc[4];
+        rate_controller(P, x.wx, x.wy, x.wz, u, Tc);
+        if (P.lag)
+            rk4_step<true>(P, x, Tc);
+        else
+            rk4_step<false>(P, x, Tc);
+    }
+    const float out[17] = {x.px, x.py, x.pz, x.qw, x.qx, x.qy, x.qz, x.vx, x.vy, x.vz,
+                           x.wx, x.wy, x.wz, x.T0, x.T1, x.T2, x.T3};
+    for (int i = 0; i < 17; ++i) x_out[i] = out[i];
+}
+
 // One workgroup writes u_apply and the shifted warm start of one instance.
 __device__ __forceinline__ void apply_shift_block(const ModelParams& P, const float* __restrict__ x_hat,
                                                   const float* __restrict__ u_upd,
                                                   float* __restrict__ u_nom,
                                                   float* __restrict__ u_apply, int N, float4 u_init,
-                                                  const mppi_diag* __restrict__ diag)
+                                                  float alpha, const mppi_diag* __restrict__ diag)
 {
     const bool ok = diag == nullptr || diag->status == MPPI_OK;
     if (threadIdx.x == 0) {
@@ -350,8 +375,14 @@ __device__ __forceinline__ void apply_shift_block(const ModelParams& P, const fl
     }
     if (!ok) return;   // all costs non-finite: keep the warm start as it was
     const float init[4] = {u_init.x, u_init.y, u_init.z, u_init.w};
-    for (int i = threadIdx.x; i < 4 * N; i += blockDim.x)
-        u_nom[i] = i < 4 * (N - 1) ? u_upd[i + 4] : init[i & 3];
+    // Knot j moves to the value at j + alpha of the linear interpolant through
+    // u_upd[0..N-1] and u_init (Sec. IV-B); alpha = 1 is the plain shift, copied exactly.
+    const bool shift = alpha == 1.0f;
+    const float keep = 1.0f - alpha;
+    for (int i = threadIdx.x; i < 4 * N; i += blockDim.x) {
+        const float next = i < 4 * (N - 1) ? u_upd[i + 4] : init[i & 3];
+        u_nom[i] = shift ? next : fmaf(alpha, next, keep * u_upd[i]);
+    }
 }
 
 }  // namespace mppi

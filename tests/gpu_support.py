@@ -49,7 +49,7 @@ class DeviceProblem:
         self.N, self.K, self.M = self.solve["N"], self.solve["K"], sc.M
         x_hat = sc.x0 if x_hat is None else x_hat
         u_nom = sc.u_nom0()[: self.N] if u_nom is None else u_nom
-        x_ref = sc.ref.rows(t * sc.dt, self.N, sc.dt)
+        x_ref = sc.ref.rows(t * sc.period, self.N, sc.dt)
         self.x_hat, self.u_nom, self.x_ref = dev(x_hat), dev(u_nom), dev(x_ref)
         self.obs = lib.obstacles_to_device(sc.obstacles)
         # what the oracle is given: the binary32 values the device holds

@@ -47,7 +47,7 @@ def test_struct_layouts():
     import paper_2407_09812_amd as lib
     assert C.sizeof(lib.Vehicle) == 13 * 4
     assert C.sizeof(lib.Cost) == 15 * 4
-    assert C.sizeof(lib.Solve) == 64 and lib.Solve.seed.offset == 48
+    assert C.sizeof(lib.Solve) == 72 and lib.Solve.seed.offset == 48 and lib.Solve.dt_ctrl.offset == 64
     assert C.sizeof(lib.Diag) == 32
     assert lib.OBSTACLE_DTYPE.itemsize == 20
 

@@ -43,6 +43,8 @@ def make_fleet(seed=44, shapes=SHAPES, paper_model_every=4):
             sc.veh = W.vehicle_paper()
             sc.x0 = W.state_on_reference(sc.ref, 0.0, sc.veh)
             sc.u_init = W.hover_control(sc.veh)
+        if i % 3 == 1:                     # warm start advanced by interpolation (Sec. IV-B)
+            sc.dt_ctrl = sc.dt / 4
         fleet.append(sc)
     return fleet
 
@@ -180,6 +182,7 @@ def test_poisoned_instance_leaves_the_others_untouched(lib, ctx):
 
 def test_batch_member_matches_oracle_end_to_end(lib, ctx, orc):
     fleet = make_fleet(seed=48, shapes=[(256, 30, 10), (300, 25, 0), (128, 40, 30)])
+    assert fleet[1].dt_ctrl > 0
     insts = []
     for sc in fleet:
         sol = sc.solve(0)

@@ -1,9 +1,12 @@
 """Serving: continuous batching of MPPI updates for many vehicles.
 
 Bars: every served result (applied control, diagnostics, final warm starts) is bit-
-identical to the same vehicle's updates run alone, in order, with mppi_update;
-requests are coalesced into batches and two slots run at once; a snapshot restores
-the exact continuation; budget and argument errors are reported.
+identical to the same vehicle's updates run alone, in order, with mppi_update --
+also with the warm start advanced by interpolation (Sec. IV-B) and the state
+estimate predicted over a delay with the vehicle's last served command (Sec. IV-E),
+run alone as mppi_predict then mppi_update; requests are coalesced into batches and
+two slots run at once; a snapshot restores the exact continuation; budget and
+argument errors are reported.
 """
 import numpy as np
 import pytest
@@ -23,7 +26,7 @@ def lib():
     return lib
 
 
-def make_requests(n_req, n_veh, seed, N_max=64, M_max=40):
+def make_requests(n_req, n_veh, seed, N_max=64, M_max=40, dt_ctrl_frac=0.0, delay=0.0):
     rng = np.random.default_rng(seed)
     fleet = [W.random_vehicle(rng, v, seed, K=64, N=N_max, M=int(rng.integers(0, M_max + 1)))
              for v in range(n_veh)]
@@ -39,7 +42,7 @@ def make_requests(n_req, n_veh, seed, N_max=64, M_max=40):
         reqs.append(dict(vid=v, K=K, N=N, dt=sc.dt, lam=sc.lam, sigma=sc.sigma, seed=seed,
                          x_hat=x_hat.astype(np.float32),
                          x_ref=sc.ref.rows(t * sc.dt, N, sc.dt).astype(np.float32),
-                         obs=sc.obstacles))
+                         obs=sc.obstacles, dt_ctrl=dt_ctrl_frac * sc.dt, delay=delay))
     return fleet, reqs
 
 
@@ -53,27 +56,35 @@ def new_server(lib, n_veh, n_streams=2, max_batch=4, budget=64 << 20, N_max=64):
 
 def submit_all(lib, srv, reqs):
     return [srv.submit(r["vid"], r["K"], r["N"], r["dt"], r["lam"], r["sigma"], r["seed"],
-                       r["x_hat"], r["x_ref"], lib.obstacles_host(r["obs"])) for r in reqs]
+                       r["x_hat"], r["x_ref"], lib.obstacles_host(r["obs"]),
+                       dt_ctrl=r.get("dt_ctrl", 0.0), delay=r.get("delay", 0.0)) for r in reqs]
 
 
 def replay_alone(lib, reqs, results, n_veh, N_max=64, warm=None, t0=None):
-    """Each vehicle's requests in order through mppi_update from its own warm start."""
+    """Each vehicle's requests in order through mppi_predict (over the delay the
+    server reports, with the vehicle's previous command) and mppi_update from its own
+    warm start."""
     veh, cost = W.vehicle_benchmark(), W.cost_benchmark()
     u_init = W.hover_control(veh)
     ctx = lib.Context(0)
     lib.mppi_reserve(ctx, 2048, N_max, 40)
     u_full = [dev(np.tile(u_init, (N_max, 1))) if warm is None else dev(warm[v]) for v in range(n_veh)]
+    hold = [dev(u_init) for _ in range(n_veh)]
     outs = []
     for r, res in zip(reqs, results):
         v, K, N = r["vid"], r["K"], r["N"]
         M = r["obs"].shape[0]
         lib.mppi_set_config(ctx, K, N, M, 64, res["lanes"], 1)
         solve = dict(K=K, N=N, dt=r["dt"], lam=r["lam"], sigma=r["sigma"], u_init=u_init,
-                     seed=r["seed"], vehicle_id=v, t=res["t"])
+                     seed=r["seed"], vehicle_id=v, t=res["t"], dt_ctrl=r.get("dt_ctrl", 0.0))
         u_apply = torch.empty(8, device="cuda")
         diag = lib.new_diag()
-        lib.mppi_update(ctx, veh, cost, solve, dev(r["x_hat"]), dev(r["x_ref"]),
+        x_hat = dev(r["x_hat"])
+        if res["delay"] > 0:
+            lib.mppi_predict(ctx, veh, r["dt"], res["delay"], x_hat, hold[v], x_hat)
+        lib.mppi_update(ctx, veh, cost, solve, x_hat, dev(r["x_ref"]),
                         lib.obstacles_to_device(r["obs"]), M, u_full[v][:N], u_apply, diag)
+        hold[v] = u_apply[:4].clone()
         torch.cuda.synchronize()
         outs.append((u_apply.cpu().numpy(), lib.diag_from_tensor(diag)))
     warm_out = np.stack([u.cpu().numpy() for u in u_full])
@@ -81,9 +92,10 @@ def replay_alone(lib, reqs, results, n_veh, N_max=64, warm=None, t0=None):
     return outs, warm_out
 
 
-def test_served_equals_alone_bitwise(lib):
+@pytest.mark.parametrize("dt_ctrl_frac,delay", [(0.0, 0.0), (0.25, 0.004)])
+def test_served_equals_alone_bitwise(lib, dt_ctrl_frac, delay):
     n_veh = 6
-    fleet, reqs = make_requests(40, n_veh, seed=61)
+    fleet, reqs = make_requests(40, n_veh, seed=61, dt_ctrl_frac=dt_ctrl_frac, delay=delay)
     srv = new_server(lib, n_veh)
     try:
         tickets = submit_all(lib, srv, reqs)
@@ -101,6 +113,7 @@ def test_served_equals_alone_bitwise(lib):
         per_vehicle_t[r["vid"]] = res["t"] + 1
     alone, warm = replay_alone(lib, reqs, results, n_veh)
     for res, (ua, dg) in zip(results, alone):
+        assert res["delay"] == np.float32(delay)
         assert np.array_equal(res["u_apply"].astype(np.float32), ua)
         assert res["rho"] == dg["rho"] and res["argmin"] == dg["argmin"] and res["ess"] == dg["ess"]
     warm_srv = snap[: warm.nbytes].view(np.float32).reshape(warm.shape)
@@ -125,8 +138,10 @@ def test_two_slots_overlap_and_batches_coalesce(lib):
 
 
 def test_snapshot_restore_continues_exactly(lib):
+    """Warm starts, last served commands (used by the delay prediction) and update
+    counters come back exactly."""
     n_veh = 4
-    _, reqs = make_requests(24, n_veh, seed=63)
+    _, reqs = make_requests(24, n_veh, seed=63, dt_ctrl_frac=0.5, delay=0.012)
     first, second = reqs[:12], reqs[12:]
     a = new_server(lib, n_veh)
     try:
@@ -145,6 +160,27 @@ def test_snapshot_restore_continues_exactly(lib):
         assert x["t"] == y["t"] and np.array_equal(x["u_apply"], y["u_apply"])
 
 
+def test_delay_from_the_served_latency(lib):
+    """delay < 0: each request is predicted over the running median of the served
+    submit-to-result latency -- 0 before any request has finished, then positive and
+    of the order of the measured latencies."""
+    n_veh = 8
+    _, reqs = make_requests(48, n_veh, seed=65, delay=-1.0)
+    srv = new_server(lib, n_veh)
+    try:
+        results = []
+        for i in range(0, 48, 8):                        # in waves, so that latencies exist
+            results += [srv.wait(t) for t in submit_all(lib, srv, reqs[i:i + 8])]
+    finally:
+        srv.close()
+    delays = np.array([r["delay"] for r in results])
+    lat = np.array([r["latency_s"] for r in results])
+    print("delays used (ms)", np.round(1e3 * delays, 3), "median latency (ms)", 1e3 * np.median(lat))
+    assert all(r["status"] == 0 and np.all(np.isfinite(r["u_apply"])) for r in results)
+    assert delays[0] == 0.0 and np.all(delays >= 0) and np.all(delays[8:] > 0)
+    assert delays.max() <= lat.max() * 1.0001
+
+
 def test_budget_and_argument_errors(lib):
     srv = new_server(lib, 3, n_streams=1, budget=1 << 20)        # 1 MiB of delta_u per slot
     try:
@@ -161,6 +197,11 @@ def test_budget_and_argument_errors(lib):
         with pytest.raises(lib.MPPIError) as e:                  # never issued
             srv.poll(12345)
         assert e.value.status == -1
+        for bad in (dict(dt_ctrl=-0.001), dict(dt_ctrl=1.0), dict(delay=float("nan")),
+                    dict(delay=1e3)):
+            with pytest.raises(lib.MPPIError) as e:
+                submit_all(lib, srv, [dict(reqs[0], **bad)])
+            assert e.value.status == -1
         assert srv.stats()["rejected"] == 1
     finally:
         srv.close()

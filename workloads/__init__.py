@@ -183,6 +183,26 @@ class CircleReference(Reference):
         return p, v, acc
 
 
+class SlantedCircleReference(Reference):
+    """Circle in a plane tilted by `tilt` about the world x axis:
+    p = c + r (cos a, sin a cos(tilt), sin a sin(tilt)), a = phase + (v / r) t."""
+
+    def __init__(self, centre, radius, speed, tilt, phase=0.0):
+        self.c = np.asarray(centre, dtype=np.float64)
+        self.r = float(radius)
+        self.om = float(speed) / float(radius)
+        self.ct, self.st = math.cos(tilt), math.sin(tilt)
+        self.phase = float(phase)
+
+    def pva(self, tau):
+        a = self.phase + self.om * np.atleast_1d(tau)
+        ca, sa = np.cos(a), np.sin(a)
+        p = self.c + self.r * np.stack([ca, sa * self.ct, sa * self.st], 1)
+        v = self.r * self.om * np.stack([-sa, ca * self.ct, ca * self.st], 1)
+        acc = -self.r * self.om ** 2 * np.stack([ca, sa * self.ct, sa * self.st], 1)
+        return p, v, acc
+
+
 def state_on_reference(ref: Reference, tau: float, veh: dict) -> np.ndarray:
     """A state estimate sitting on the reference, rotors at the reference thrust."""
     row = ref.row(tau)
@@ -215,6 +235,21 @@ def cylinders_off_circle(rng: np.random.Generator, M: int, area_lo, area_hi, cen
     return np.array(out, dtype=np.float64).reshape(-1, 5)
 
 
+def cylinders_off_path(rng: np.random.Generator, M: int, area_lo, area_hi, path_xy,
+                       r_lo=0.2, r_hi=0.6, clearance=1.0) -> np.ndarray:
+    """Vertical cylinders uniform in an area, rejected while closer than r + clearance
+    to any of the path's sampled xy points."""
+    out = []
+    path_xy = np.asarray(path_xy, float)
+    while len(out) < M:
+        cxy = rng.uniform(area_lo, area_hi, size=2)
+        r = rng.uniform(r_lo, r_hi)
+        if np.min(np.linalg.norm(path_xy - cxy, axis=1)) < r + clearance:
+            continue
+        out.append([VCYL, cxy[0], cxy[1], 0.0, r])
+    return np.array(out, dtype=np.float64).reshape(-1, 5)
+
+
 # ---------------------------------------------------------------------------
 # Benchmark configurations
 # ---------------------------------------------------------------------------
@@ -223,9 +258,10 @@ class Scenario:
     """One vehicle's MPPI problem: parameters, reference, obstacles, start."""
 
     def __init__(self, name, veh, cost, K, N, dt, lam, sigma, seed, vehicle_id, ref, obstacles,
-                 updates, x0=None):
+                 updates, x0=None, dt_ctrl=0.0):
         self.name, self.veh, self.cost = name, veh, cost
         self.K, self.N, self.dt, self.lam = int(K), int(N), float(dt), float(lam)
+        self.dt_ctrl = float(dt_ctrl)            # time between updates; 0: dt
         self.sigma = np.asarray(sigma, dtype=np.float64)
         self.seed, self.vehicle_id = int(seed), int(vehicle_id)
         self.ref = ref
@@ -238,12 +274,19 @@ class Scenario:
     def M(self):
         return self.obstacles.shape[0]
 
+    @property
+    def period(self) -> float:
+        """Time between consecutive updates (the closed loop's plant step)."""
+        return self.dt_ctrl if self.dt_ctrl > 0 else self.dt
+
     def solve(self, t: int = 0) -> dict:
         return dict(K=self.K, N=self.N, dt=self.dt, lam=self.lam, sigma=self.sigma,
-                    seed=self.seed, vehicle_id=self.vehicle_id, t=int(t), u_init=self.u_init)
+                    seed=self.seed, vehicle_id=self.vehicle_id, t=int(t), u_init=self.u_init,
+                    dt_ctrl=self.dt_ctrl)
 
     def x_ref(self, t: int = 0) -> np.ndarray:
-        return self.ref.rows(t * self.dt, self.N, self.dt)
+        """Reference rows at the prediction steps from the time of update t."""
+        return self.ref.rows(t * self.period, self.N, self.dt)
 
     def u_nom0(self) -> np.ndarray:
         return np.tile(self.u_init, (self.N, 1))
@@ -279,6 +322,26 @@ def c3_agile(K=16384, N=200, seed=3) -> Scenario:
     return Scenario("c3_agile", vehicle_benchmark(), cost_benchmark(), K, N, 0.01, 1.0,
                     (1.0, 1.0, 1.0, 1.0), seed=seed, vehicle_id=0, ref=ref, obstacles=obs,
                     updates=200)
+
+
+def paper_preset(K=896, N=15, seed=6) -> Scenario:
+    """The paper's own setting: Table I vehicle (simulation limits, no rotor lag),
+    Table II parameters (prediction step 0.1 s, K = 896, N = 15, lambda = 1e-4,
+    Sigma = diag(0.60, 0.15, 0.15, 0.05) read as variances), updates every 10 ms with
+    the warm start advanced by interpolation (Sec. IV-B, n = 10), and the
+    indicator-only obstacle cost with c_obs = 1e6 (Sec. IV-D).  The path is a circle
+    of radius 6.04 m tilted by 30 degrees at 5.65 m/s (5.29 m/s^2, the speed and
+    acceleration of the slanted-circle trajectory in Table III) among 40 pillar-like
+    vertical cylinders kept 1 m off its ground track."""
+    rng = np.random.default_rng(seed)
+    centre = (0.0, 0.0, 4.0)
+    ref = SlantedCircleReference(centre, 6.04, 5.65, math.radians(30.0))
+    track = ref.pva(np.linspace(0.0, 2 * math.pi / ref.om, 400))[0][:, :2]
+    obs = cylinders_off_path(rng, 40, -12.0, 12.0, track, r_lo=0.3, r_hi=0.8)
+    veh = vehicle_paper()
+    return Scenario("paper_preset", veh, cost_paper(), K, N, 0.1, 1e-4,
+                    np.sqrt([0.60, 0.15, 0.15, 0.05]), seed=seed, vehicle_id=0, ref=ref,
+                    obstacles=obs, updates=300, dt_ctrl=0.01)
 
 
 K_SET = (1024, 2048, 4096, 8192, 16384)
@@ -329,4 +392,4 @@ def c5_arrivals(rate_hz=2000.0, duration_s=60.0, n_vehicles=512, seed=5):
     return fleet, out
 
 
-CONFIGS = {"c1": c1_plain, "c2": c2_line, "c3": c3_agile}
+CONFIGS = {"c1": c1_plain, "c2": c2_line, "c3": c3_agile, "paper": paper_preset}
