@@ -81,7 +81,7 @@ def rollout_flop_per_launch(K: int, N: int, M: int, obstacle_tests: float) -> fl
 
 
 def reduction_bytes_per_launch(K: int, N: int) -> float:
-    # delta_u [N][4][K] read once, weights [K] once, u_nom read and u_upd written
+    # delta_u [N][4][K] read once, costs [K] once, u_nom read and u_upd written
     return 4.0 * (4 * K * N + K + 8 * N)
 
 
@@ -172,6 +172,9 @@ def run(args):
                                    reps=3, stream=stream)
     else:
         launch = lib.mppi_get_config(ctx, K, N, M)
+    if args.variant != "auto":                   # force stored delta_u or the single pass
+        launch = dict(launch, fused=1 if args.variant == "fused" else 0)
+        lib.mppi_set_config(ctx, K, N, M, **launch)
     log(f"bench: rollout launch shape {launch}")
 
     lat = []
@@ -214,7 +217,7 @@ def run(args):
     value = K * N * steps / elapsed
     n_upd = max(1, prof["updates"])
     rollout_ms = prof["rollout_ms"] / n_upd
-    reduce_ms = prof["reduce_ms"] / n_upd
+    sum_ms = prof["sum_ms"] / n_upd
     tests = prof["obstacle_tests"] / n_upd
     flop = rollout_flop_per_launch(K, N, M, tests)
     achieved = flop / (rollout_ms * 1e-3)
@@ -238,8 +241,7 @@ def run(args):
                    "K": K, "N": N, "M": M, "updates": steps, "rollout_launch": launch},
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99),
                        "mean": sum(lat) / len(lat)},
-        "device_ms_per_update": {"rollout": rollout_ms, "weights": prof["weights_ms"] / n_upd,
-                                 "reduce": reduce_ms, "apply": prof["apply_ms"] / n_upd},
+        "device_ms_per_update": {"rollout": rollout_ms, "sum_and_apply": sum_ms},
         "roofline": {
             "kernel": "rollout_kernel",
             "bound": "alu",
@@ -252,10 +254,14 @@ def run(args):
             "obstacle_tests_per_state": tests / (K * (N + 1)),
             "traffic": measured_traffic(K, N, M),
         },
-        "reduction": {"kernel": "weighted_sum_kernel", "bound": "hbm",
-                      "achieved": rbytes / (reduce_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
-                      "unit": "GB/s", "frac": rbytes / (reduce_ms * 1e-3) / PEAK_HBM,
-                      "bytes_per_launch": rbytes},
+        "reduction": ({"kernel": "update_sum_kernel", "bound": "hbm",
+                       "achieved": rbytes / (sum_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
+                       "unit": "GB/s", "frac": rbytes / (sum_ms * 1e-3) / PEAK_HBM,
+                       "bytes_per_launch": rbytes}
+                      if not launch.get("fused") else
+                      {"kernel": "merge_sum_kernel", "bound": "latency",
+                       "note": "single pass: delta_u is regenerated in the rollout launch, not "
+                               "stored; this launch sums the per-wave partials"}),
     }
     ctx.close()
     if args.cpu_seconds > 0:
@@ -501,6 +507,9 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=20,
                     help="batched updates of the 256-vehicle mix timed beside the plain line "
                          "(0 skips the batched leg)")
+    ap.add_argument("--variant", default="auto", choices=["auto", "stored", "fused"],
+                    help="update variant of the single-vehicle leg: the autotuner's choice, "
+                         "stored delta_u + weighted sum, or the single pass")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="use the library's default rollout launch shape")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,

@@ -229,12 +229,19 @@ mppi_status mppi_plant_step(mppi_ctx *ctx, void *stream, const mppi_vehicle *veh
 
 /* Shape of the rollout launch: `lanes` consecutive lanes share one sample and divide
  * its obstacle tests (1, 2, 4, 8); `block` threads per workgroup (64, 128, 256);
- * obstacle loop unrolled `unroll` times (1, 4).  Every shape computes the same update;
- * only the order of the obstacle-penalty additions (hence rounding) depends on lanes. */
+ * obstacle loop unrolled `unroll` times (1, 4).  fused = 1 selects the single-pass
+ * update (Eqs. (4), (5) without delta_u in memory): each wave of the rollout launch
+ * ends by forming its own minimum cost rho_w, its weights relative to it and its
+ * partial sums of e_k delta_u (the perturbations regenerated from the counter-based
+ * noise), and one merge launch rescales the partials by exp(-(rho_w - rho)/lambda);
+ * fused = 0 stores delta_u and runs the weights and the GEMV-shaped weighted sum.
+ * Every shape computes the same update up to rounding: the order of the obstacle-
+ * penalty additions depends on lanes, and the order of the weighted sums on fused. */
 typedef struct mppi_launch_config {
     int32_t block;
     int32_t lanes;
     int32_t unroll;
+    int32_t fused;
 } mppi_launch_config;
 
 /* The shape mppi_update / mppi_rollout use for (K, N, M): a stored entry for the
@@ -246,8 +253,9 @@ mppi_status mppi_get_config(const mppi_ctx *ctx, int32_t K, int32_t N, int32_t M
  * outside the lists above.  Host-only. */
 mppi_status mppi_set_config(mppi_ctx *ctx, int32_t K, int32_t N, int32_t M,
                             const mppi_launch_config *cfg);
-/* Time every shape on these inputs (reps launches each, HIP events on `stream`),
- * store the fastest for the size class and return it in best.  Uses the context's
+/* Time every shape, both variants, on these inputs (reps runs each of the rollouts
+ * through the updated sequence, HIP events on `stream`), store the fastest for the
+ * size class and return it in best.  Uses the context's
  * scratch (mppi_reserve first) and synchronises the stream; a set-up call, not for
  * the update loop. */
 mppi_status mppi_autotune(mppi_ctx *ctx, void *stream, const mppi_vehicle *veh,
@@ -398,13 +406,16 @@ mppi_status mppi_server_restore(mppi_server *srv, const void *host_buf, size_t s
 
 /* --- profiling ---------------------------------------------------------------- */
 
-/* Per-kernel device time of mppi_update, and of mppi_batch_update's rollout stage and
- * remaining stages, measured with HIP events on the call's stream while enabled.
- * While profiling, batches are launched kernel by kernel (no graph replay) so that
- * the events can bracket the rollout stage. */
+/* Device time of mppi_update's two launches -- rollout_ms: the rollouts with the
+ * weight statistics their last workgroup reduces; sum_ms: the weighted sum (stored
+ * delta_u or single-pass partial sums) with the apply and advance of its last
+ * workgroup -- and of mppi_batch_update's rollout stage and remaining stages, measured
+ * with HIP events on the call's stream while enabled.  While profiling, batches are
+ * launched kernel by kernel (no graph replay) so that the events can bracket the
+ * rollout stage. */
 typedef struct mppi_profile {
     int64_t updates;
-    double rollout_ms, weights_ms, reduce_ms, apply_ms;
+    double rollout_ms, sum_ms;
     int64_t batches;
     double batch_rollout_ms, batch_rest_ms;
     int64_t obstacle_tests;   /* sample-state-obstacle distance tests performed (both paths);

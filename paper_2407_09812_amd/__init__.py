@@ -66,7 +66,8 @@ class Diag(C.Structure):
 
 
 class LaunchConfig(C.Structure):
-    _fields_ = [("block", C.c_int32), ("lanes", C.c_int32), ("unroll", C.c_int32)]
+    _fields_ = [("block", C.c_int32), ("lanes", C.c_int32), ("unroll", C.c_int32),
+                ("fused", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -109,8 +110,8 @@ class ServerStats(C.Structure):
 
 
 class Profile(C.Structure):
-    _fields_ = [("updates", C.c_int64), ("rollout_ms", C.c_double), ("weights_ms", C.c_double),
-                ("reduce_ms", C.c_double), ("apply_ms", C.c_double), ("batches", C.c_int64),
+    _fields_ = [("updates", C.c_int64), ("rollout_ms", C.c_double), ("sum_ms", C.c_double),
+                ("batches", C.c_int64),
                 ("batch_rollout_ms", C.c_double), ("batch_rest_ms", C.c_double),
                 ("obstacle_tests", C.c_int64)]
 
@@ -358,11 +359,11 @@ def mppi_predict(ctx, veh, dt, delay, x_hat, u_hold, x_out, stream=None):
 def mppi_get_config(ctx, K, N, M) -> dict:
     c = LaunchConfig()
     ctx.check(_lib.mppi_get_config(ctx.handle, int(K), int(N), int(M), C.byref(c)), "mppi_get_config")
-    return dict(block=c.block, lanes=c.lanes, unroll=c.unroll)
+    return dict(block=c.block, lanes=c.lanes, unroll=c.unroll, fused=c.fused)
 
 
-def mppi_set_config(ctx, K, N, M, block, lanes, unroll):
-    c = LaunchConfig(int(block), int(lanes), int(unroll))
+def mppi_set_config(ctx, K, N, M, block, lanes, unroll, fused=0):
+    c = LaunchConfig(int(block), int(lanes), int(unroll), int(fused))
     ctx.check(_lib.mppi_set_config(ctx.handle, int(K), int(N), int(M), C.byref(c)), "mppi_set_config")
 
 
@@ -372,7 +373,7 @@ def mppi_autotune(ctx, veh, cst, slv, x_hat, x_ref, obs_dev, M, u_nom, reps=3, s
     ctx.check(_lib.mppi_autotune(ctx.handle, _stream(stream), C.byref(v), C.byref(c), C.byref(s),
                                  _ptr(x_hat), _ptr(x_ref), _ptr(obs_dev) if M > 0 else None,
                                  int(M), _ptr(u_nom), int(reps), C.byref(best)), "mppi_autotune")
-    return dict(block=best.block, lanes=best.lanes, unroll=best.unroll)
+    return dict(block=best.block, lanes=best.lanes, unroll=best.unroll, fused=best.fused)
 
 
 def make_requests(items) -> C.Array:
@@ -429,8 +430,7 @@ def mppi_profile_enable(ctx, on=True):
 def mppi_profile_read(ctx) -> dict:
     p = Profile()
     ctx.check(_lib.mppi_profile_read(ctx.handle, C.byref(p)), "mppi_profile_read")
-    return dict(updates=p.updates, rollout_ms=p.rollout_ms, weights_ms=p.weights_ms,
-                reduce_ms=p.reduce_ms, apply_ms=p.apply_ms, batches=p.batches,
+    return dict(updates=p.updates, rollout_ms=p.rollout_ms, sum_ms=p.sum_ms, batches=p.batches,
                 batch_rollout_ms=p.batch_rollout_ms, batch_rest_ms=p.batch_rest_ms,
                 obstacle_tests=p.obstacle_tests)
 

@@ -165,16 +165,26 @@ RolloutArgs rollout_args(const mppi_vehicle& v, const mppi_cost& c, const mppi_s
 
 namespace {
 
-constexpr int kEventsPerUpdate = 5;
+constexpr int kEventsPerUpdate = 3;   // before, between and after the two launches
 
 void free_scratch(mppi_ctx* ctx)
 {
     (void)hipFree(ctx->du); (void)hipFree(ctx->S); (void)hipFree(ctx->w);
     (void)hipFree(ctx->u_upd); (void)hipFree(ctx->diag);
-    ctx->du = ctx->S = ctx->w = ctx->u_upd = nullptr;
+    (void)hipFree(ctx->wstat); (void)hipFree(ctx->part); (void)hipFree(ctx->rho_run);
+    (void)hipFree(ctx->counters); (void)hipFree(ctx->list_idx); (void)hipFree(ctx->list_s);
+    (void)hipFree(ctx->list_n); (void)hipFree(ctx->u_tmp);
+    ctx->rho_run = ctx->counters = nullptr;
+    ctx->list_idx = ctx->list_n = nullptr;
+    ctx->list_s = ctx->u_tmp = nullptr;
+    ctx->du = ctx->S = ctx->w = ctx->u_upd = ctx->part = nullptr;
     ctx->diag = nullptr;
+    ctx->wstat = nullptr;
+    ctx->W_cap = 0;
     ctx->K_cap = ctx->N_cap = ctx->M_cap = ctx->ld = 0;
 }
+
+constexpr unsigned int kInfBits = 0x7f800000u;
 
 int ceil_log2(int v)
 {
@@ -221,6 +231,61 @@ hipEvent_t mppi::take_event(mppi_ctx* ctx)
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
 }
+
+namespace {
+
+// The full update in two launches on stream s: the rollouts with the weight
+// statistics (reduced by their last workgroup into dg), then the weighted sum into
+// ctx->u_upd whose last workgroup applies and advances as `ap` says; either over the
+// stored delta_u or, with cfg.fused, over the per-wave partial sums.  mark(1) is
+// called between the two launches.
+template <typename Mark>
+hipError_t update_core(mppi_ctx* ctx, const RolloutArgs& a, const LaunchConfig& cfg, float lambda,
+                       const float* u_in, const ApplyArgs& ap, mppi_diag* dg, hipStream_t s,
+                       Mark mark)
+{
+    UpdateTail tail;
+    tail.lambda = lambda;
+    tail.stat = ctx->wstat;
+    tail.counter = ctx->counters;
+    tail.diag = dg;
+    hipError_t e;
+    if (cfg.fused) {
+        tail.part = ctx->part;
+        tail.rho_run = ctx->rho_run;
+        tail.list_idx = ctx->list_idx;
+        tail.list_s = ctx->list_s;
+        tail.list_n = ctx->list_n;
+        e = launch_rollout_fused(a, cfg, tail, s);
+        if (e == hipSuccess) e = mark(1);
+        if (e == hipSuccess)
+            e = launch_merge_sum(ctx->part, a.N, ctx->list_idx, ctx->list_s, ctx->list_n, u_in,
+                                 ctx->u_upd, dg, ap, ctx->counters + 1, s);
+    } else {
+        e = launch_rollout(a, cfg, s, &tail);
+        if (e == hipSuccess) e = mark(1);
+        if (e == hipSuccess)
+            e = launch_update_sum(ctx->S, ctx->du, a.K, a.N, ctx->ld, lambda, u_in, ctx->u_upd, dg, ap,
+                                  ctx->counters + 1, s);
+    }
+    return e;
+}
+
+ApplyArgs apply_args(const ModelParams& P, const float* x_hat, float* u_nom, float* u_apply, int N,
+                     const mppi_solve& solve)
+{
+    ApplyArgs ap;
+    ap.P = P;
+    ap.x_hat = x_hat;
+    ap.u_nom = u_nom;
+    ap.u_apply = u_apply;
+    ap.N = N;
+    ap.u_init = make_float4(solve.u_init[0], solve.u_init[1], solve.u_init[2], solve.u_init[3]);
+    ap.alpha = advance_fraction(solve);
+    return ap;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -307,15 +372,28 @@ mppi_status mppi_reserve(mppi_ctx* ctx, int32_t K, int32_t N, int32_t M)
     free_scratch(ctx);
     const int ld = (Kc + 63) & ~63;   // rows start on 256-byte boundaries
     const size_t du_bytes = sizeof(float) * (size_t)Nc * 4 * ld;
+    // the most waves a rollout launch has: 8 lanes per sample, whole workgroups of 256
+    const int W = (int)(((size_t)ld * 8 + 255) / 256 * 4);
     if (hipMalloc(&ctx->du, du_bytes) != hipSuccess || hipMalloc(&ctx->S, sizeof(float) * ld) != hipSuccess ||
         hipMalloc(&ctx->w, sizeof(float) * ld) != hipSuccess ||
         hipMalloc(&ctx->u_upd, sizeof(float) * 4 * (size_t)Nc) != hipSuccess ||
-        hipMalloc(&ctx->diag, sizeof(mppi_diag)) != hipSuccess) {
+        hipMalloc(&ctx->diag, sizeof(mppi_diag)) != hipSuccess ||
+        hipMalloc(&ctx->wstat, sizeof(WaveStat) * (size_t)W) != hipSuccess ||
+        hipMalloc(&ctx->part, sizeof(float) * 4 * (size_t)Nc * W) != hipSuccess ||
+        hipMalloc(&ctx->rho_run, sizeof(unsigned int)) != hipSuccess ||
+        hipMemcpy(ctx->rho_run, &kInfBits, sizeof(unsigned int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMalloc(&ctx->counters, 2 * sizeof(unsigned int)) != hipSuccess ||
+        hipMemset(ctx->counters, 0, 2 * sizeof(unsigned int)) != hipSuccess ||
+        hipMalloc(&ctx->list_idx, sizeof(int) * (size_t)W) != hipSuccess ||
+        hipMalloc(&ctx->list_s, sizeof(float) * (size_t)W) != hipSuccess ||
+        hipMalloc(&ctx->list_n, sizeof(int)) != hipSuccess ||
+        hipMalloc(&ctx->u_tmp, sizeof(float) * (4 * (size_t)Nc + 8)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
         free_scratch(ctx);
         (void)hipGetLastError();
         return fail(ctx, MPPI_E_OOM, "reserve: device allocation failed");
     }
-    ctx->K_cap = Kc; ctx->N_cap = Nc; ctx->M_cap = Mc; ctx->ld = ld;
+    ctx->K_cap = Kc; ctx->N_cap = Nc; ctx->M_cap = Mc; ctx->ld = ld; ctx->W_cap = W;
     return MPPI_OK;
 }
 
@@ -348,17 +426,10 @@ mppi_status mppi_update(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh, co
     };
 
     const LaunchConfig cfg = config_for(ctx, solve->K, solve->N, M);
+    const ApplyArgs ap = apply_args(a.mp, x_hat, u_nom, u_apply, solve->N, *solve);
     HIP_TRY(ctx, mark(0));
-    HIP_TRY(ctx, launch_rollout(a, cfg, s));
-    HIP_TRY(ctx, mark(1));
-    HIP_TRY(ctx, launch_weights(ctx->S, solve->K, solve->lambda, ctx->w, dg, cfg.lanes, s));
+    HIP_TRY(ctx, update_core(ctx, a, cfg, solve->lambda, u_nom, ap, dg, s, mark));
     HIP_TRY(ctx, mark(2));
-    HIP_TRY(ctx, launch_weighted_sum(ctx->w, ctx->du, solve->K, solve->N, ctx->ld, u_nom,
-                                     ctx->u_upd, dg, s));
-    HIP_TRY(ctx, mark(3));
-    HIP_TRY(ctx, launch_apply_shift(a.mp, x_hat, ctx->u_upd, u_nom, u_apply, solve->N,
-                                    solve->u_init, advance_fraction(*solve), dg, s));
-    HIP_TRY(ctx, mark(4));
     if (ctx->profiling)
         for (int i = 0; i < kEventsPerUpdate; ++i) ctx->pending.push_back(ev[i]);
     return MPPI_OK;
@@ -386,7 +457,7 @@ mppi_status mppi_get_config(const mppi_ctx* ctx, int32_t K, int32_t N, int32_t M
 {
     if (!ctx || !out || K < 1 || N < 1 || M < 0) return MPPI_E_INVALID_ARG;
     const LaunchConfig c = config_for(ctx, K, N, M);
-    out->block = c.block; out->lanes = c.lanes; out->unroll = c.unroll;
+    out->block = c.block; out->lanes = c.lanes; out->unroll = c.unroll; out->fused = c.fused;
     return MPPI_OK;
 }
 
@@ -394,7 +465,7 @@ mppi_status mppi_set_config(mppi_ctx* ctx, int32_t K, int32_t N, int32_t M,
                             const mppi_launch_config* cfg)
 {
     if (!ctx || !cfg || K < 1 || N < 1 || M < 0) return MPPI_E_INVALID_ARG;
-    const LaunchConfig c{cfg->block, cfg->lanes, cfg->unroll};
+    const LaunchConfig c{cfg->block, cfg->lanes, cfg->unroll, cfg->fused};
     if (!valid_config(c)) return fail(ctx, MPPI_E_INVALID_ARG, "set_config: invalid shape");
     ctx->tuned[size_class(K, N, M)] = c;
     return MPPI_OK;
@@ -418,32 +489,45 @@ mppi_status mppi_autotune(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh, 
     a.du = ctx->du; a.ld = ctx->ld; a.S = ctx->S; a.states = nullptr;
     hipEvent_t e0 = take_event(ctx), e1 = take_event(ctx);
     if (!e0 || !e1) return fail(ctx, MPPI_E_HIP, "autotune: event creation");
+    // what is timed: the whole update, both variants, writing its outputs to scratch
+    const ApplyArgs ap = apply_args(a.mp, x_hat, ctx->u_tmp, ctx->u_tmp + 4 * (size_t)solve->N,
+                                    solve->N, *solve);
+    auto core = [&](const LaunchConfig& c) -> hipError_t {
+        return update_core(ctx, a, c, solve->lambda, u_nom, ap, ctx->diag, s,
+                           [](int) { return hipSuccess; });
+    };
+    std::vector<LaunchConfig> cands;
+    for (int fused : {0, 1})
+        for (int lanes : {1, 2, 4, 8}) {
+            if (lanes > 1 && M < 2 * lanes) continue;        // nothing to divide
+            for (int block : {64, 128, 256})
+                for (int unroll : {1, 4}) {
+                    if (unroll > 1 && M < 8) continue;
+                    cands.push_back(LaunchConfig{block, lanes, unroll, fused});
+                }
+        }
     LaunchConfig best_c{};
     float best_ms = 1e30f;
     mppi_status result = MPPI_OK;
-    for (int lanes : {1, 2, 4, 8}) {
-        if (lanes > 1 && M < 2 * lanes) continue;        // nothing to divide
-        for (int block : {64, 128, 256})
-            for (int unroll : {1, 4}) {
-                if (unroll > 1 && M < 8) continue;
-                const LaunchConfig c{block, lanes, unroll};
-                hipError_t e = launch_rollout(a, c, s);   // warm-up
-                if (e == hipSuccess) e = hipEventRecord(e0, s);
-                for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_rollout(a, c, s);
-                if (e == hipSuccess) e = hipEventRecord(e1, s);
-                if (e == hipSuccess) e = hipEventSynchronize(e1);
-                float ms = 0.0f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                if (e != hipSuccess) { result = hip_fail(ctx, e, "autotune"); break; }
-                if (ms < best_ms) { best_ms = ms; best_c = c; }
-            }
-        if (result != MPPI_OK) break;
+    for (const LaunchConfig& c : cands) {
+        hipError_t e = core(c);                           // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = core(c);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) { result = hip_fail(ctx, e, "autotune"); break; }
+        if (ms < best_ms) { best_ms = ms; best_c = c; }
     }
     ctx->pool.push_back(e0);
     ctx->pool.push_back(e1);
     if (result != MPPI_OK) return result;
     ctx->tuned[size_class(solve->K, solve->N, M)] = best_c;
-    if (best) { best->block = best_c.block; best->lanes = best_c.lanes; best->unroll = best_c.unroll; }
+    if (best) {
+        best->block = best_c.block; best->lanes = best_c.lanes; best->unroll = best_c.unroll;
+        best->fused = best_c.fused;
+    }
     return MPPI_OK;
 }
 
@@ -556,13 +640,11 @@ mppi_status mppi_profile_read(mppi_ctx* ctx, mppi_profile* out)
     for (size_t b = 0; b + kEventsPerUpdate <= ctx->pending.size(); b += kEventsPerUpdate) {
         hipEvent_t* e = &ctx->pending[b];
         HIP_TRY(ctx, hipEventSynchronize(e[kEventsPerUpdate - 1]));
-        float t[4];
-        for (int i = 0; i < 4; ++i) HIP_TRY(ctx, hipEventElapsedTime(&t[i], e[i], e[i + 1]));
+        float t[2];
+        for (int i = 0; i < 2; ++i) HIP_TRY(ctx, hipEventElapsedTime(&t[i], e[i], e[i + 1]));
         ctx->acc.updates += 1;
         ctx->acc.rollout_ms += t[0];
-        ctx->acc.weights_ms += t[1];
-        ctx->acc.reduce_ms += t[2];
-        ctx->acc.apply_ms += t[3];
+        ctx->acc.sum_ms += t[1];
     }
     for (hipEvent_t e : ctx->pending) ctx->pool.push_back(e);
     ctx->pending.clear();

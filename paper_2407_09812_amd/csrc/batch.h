@@ -26,8 +26,9 @@ struct InstanceDesc {
     mppi_diag* diag;
     float* du;                   // [N][4][ld]
     float* S;                    // [ld]
-    float* w;                    // [ld]
     float* u_upd;                // [N][4]
+    WaveStat* stat;              // [W] weight statistics of the rollout waves
+    int W;                       // waves of its tiles: (sample tiles) * block / 64
 };
 
 // A tile of consecutive samples of one instance: the unit the persistent rollout
@@ -53,13 +54,14 @@ struct BatchLaunch {
 
 bool valid_batch_launch(const BatchLaunch& c);
 
-// All five stages on `stream`: queue reset, persistent rollouts, per-instance weights,
-// persistent weighted sum, per-instance apply/shift.  Grid sizes depend only on
-// (cu_count, n_cap, cfg), so the sequence can be captured once and replayed.
+// All five stages on `stream`: queue reset, persistent rollouts (with the waves'
+// weight statistics), per-instance statistics reduction, persistent weighted sum,
+// per-instance apply and advance.  Grid sizes depend only on (cu_count, n_cap, cfg),
+// so the sequence can be captured once and replayed.
 hipError_t launch_batch(BatchHeader* hdr, const InstanceDesc* descs, const WorkItem* items,
                         int n_cap, int cu_count, int lds_bytes, const BatchLaunch& cfg,
                         hipStream_t stream);
-// The weights, weighted-sum and apply/shift stages.
+// The statistics, weighted-sum and apply stages.
 hipError_t launch_batch_tail(BatchHeader* hdr, const InstanceDesc* descs, int n_cap, int cu_count,
                              hipStream_t stream);
 // Only the reset and the rollout stage (autotuning).

@@ -4,13 +4,16 @@
 //                          captured in a HIP graph without memset nodes)
 //   batch_rollout_kernel   persistent: each workgroup pulls (instance, sample tile)
 //                          items, longest first, from a device queue, stages that
-//                          instance's obstacles in LDS and rolls the tile out
-//   batch_weights_kernel   one 1024-thread workgroup per instance
+//                          instance's obstacles in LDS, rolls the tile out and writes
+//                          its waves' weight statistics
+//   batch_stats_kernel     one wave per instance reduces its weight statistics
 //   batch_wsum_kernel      persistent over all instances' delta_u rows
-//   batch_apply_kernel     one workgroup per instance
+//   batch_apply_kernel     one workgroup per instance applies and advances
 // Every stage calls the same device bodies as the one-instance kernels, so an
 // instance's results are bit-identical alone and inside a batch (for the same
-// lanes-per-sample).
+// lanes-per-sample).  Unlike the one-instance launches, the stages are separate
+// kernels rather than last-arrival tails: a batch has too many tiles and rows for a
+// device-scope fence on each.
 #include <hip/hip_runtime.h>
 
 #include "batch.h"
@@ -27,12 +30,15 @@ template <int L, int U>
 __device__ __forceinline__ void batch_tile(const InstanceDesc& D, int k0, const float4* obs_lds)
 {
     const int k = k0 + (int)threadIdx.x / L, q = (int)threadIdx.x % L;
-    if (D.rp.mp.lag)
-        rollout_sample<L, U, true, false>(D.rp, D.x_hat, D.x_ref, D.u_nom, D.du, D.S, nullptr,
-                                          obs_lds, k, q);
-    else
-        rollout_sample<L, U, false, false>(D.rp, D.x_hat, D.x_ref, D.u_nom, D.du, D.S, nullptr,
-                                           obs_lds, k, q);
+    const float S = D.rp.mp.lag
+        ? rollout_sample<L, U, true, false>(D.rp, D.x_hat, D.x_ref, D.u_nom, D.du, D.S, nullptr,
+                                            obs_lds, k, q)
+        : rollout_sample<L, U, false, false>(D.rp, D.x_hat, D.x_ref, D.u_nom, D.du, D.S, nullptr,
+                                             obs_lds, k, q);
+    // the tile starts at sample k0 = (tile index) * blockDim / L: the same waves as
+    // a one-instance launch of this workgroup size
+    write_wave_stat(D.stat + ((k0 * L + (int)threadIdx.x) >> 6),
+                    wave_sums(S, k, q, k < D.rp.K, D.lambda), false);
 }
 
 template <int U>
@@ -65,13 +71,13 @@ __global__ __launch_bounds__(256) void batch_rollout_kernel(BatchHeader* hdr,
     }
 }
 
-__global__ __launch_bounds__(kWeightsThreads) void batch_weights_kernel(
-    const BatchHeader* __restrict__ hdr, const InstanceDesc* __restrict__ descs)
+__global__ __launch_bounds__(64) void batch_stats_kernel(const BatchHeader* __restrict__ hdr,
+                                                        const InstanceDesc* __restrict__ descs)
 {
     const int i = blockIdx.x;
     if (i >= hdr->n_inst) return;
     const InstanceDesc& D = descs[i];
-    weights_block(D.S, D.rp.K, D.lambda, D.w, D.diag, D.lanes);
+    reduce_wave_stats(D.stat, D.W, D.lambda, D.lanes, D.diag, nullptr, nullptr, nullptr);
 }
 
 __global__ __launch_bounds__(kSumThreads) void batch_wsum_kernel(const BatchHeader* __restrict__ hdr,
@@ -85,7 +91,8 @@ __global__ __launch_bounds__(kSumThreads) void batch_wsum_kernel(const BatchHead
             if (descs[mid].row0 <= r) lo = mid; else hi = mid - 1;
         }
         const InstanceDesc& D = descs[lo];
-        weighted_sum_row(D.w, D.du, D.rp.K, D.rp.ld, D.u_nom, D.u_upd, D.diag, r - D.row0);
+        update_sum_row(D.S, D.du, D.rp.K, D.rp.ld, D.lambda, D.u_nom, D.u_upd, D.diag, r - D.row0);
+        __syncthreads();                       // the row's LDS partials are reused
     }
 }
 
@@ -138,8 +145,7 @@ hipError_t launch_batch(BatchHeader* hdr, const InstanceDesc* descs, const WorkI
 hipError_t launch_batch_tail(BatchHeader* hdr, const InstanceDesc* descs, int n_cap, int cu_count,
                              hipStream_t stream)
 {
-    hipLaunchKernelGGL(batch_weights_kernel, dim3(n_cap), dim3(kWeightsThreads), 0, stream, hdr,
-                       descs);
+    hipLaunchKernelGGL(batch_stats_kernel, dim3(n_cap), dim3(64), 0, stream, hdr, descs);
     hipLaunchKernelGGL(batch_wsum_kernel, dim3(cu_count * 8), dim3(kSumThreads), 0, stream, hdr,
                        descs);
     hipLaunchKernelGGL(batch_apply_kernel, dim3(n_cap), dim3(256), 0, stream, hdr, descs);

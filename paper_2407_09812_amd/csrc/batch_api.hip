@@ -72,8 +72,10 @@ void destroy_graph(BatchState& b)
     b.graph_exec = nullptr;
 }
 
-// Fill the pinned plan for `cfg`; returns the number of bytes to upload.
-size_t fill_plan(mppi_ctx* ctx, const mppi_request* reqs, int n, const BatchLaunch& cfg)
+// Fill the pinned plan for `cfg`; returns the number of bytes to upload.  own_diags:
+// every instance reports into the arena's diagnostics (autotuning), not the caller's.
+size_t fill_plan(mppi_ctx* ctx, const mppi_request* reqs, int n, const BatchLaunch& cfg,
+                 bool own_diags)
 {
     BatchState& b = ctx->batch;
     const PlanLayout L = plan_layout(b.n_cap, b.items_cap);
@@ -90,7 +92,7 @@ size_t fill_plan(mppi_ctx* ctx, const mppi_request* reqs, int n, const BatchLaun
         for (int i = 0; i < n; ++i) waves += (reqs[i].solve.K + 63) / 64;
         while (auto_lanes < 8 && waves * auto_lanes * 2 <= 1024) auto_lanes *= 2;
     }
-    size_t du_off = 0, k_off = 0, u_off = 0;
+    size_t du_off = 0, k_off = 0, u_off = 0, st_off = 0;
     int row = 0;
     struct Keyed { long long cost; int inst, k0; };
     std::vector<Keyed> work;
@@ -116,9 +118,12 @@ size_t fill_plan(mppi_ctx* ctx, const mppi_request* reqs, int n, const BatchLaun
         const int tile = cfg.block / lanes;
         D.x_hat = q.x_hat; D.x_ref = q.x_ref; D.obs = q.obs;
         D.u_nom = q.u_nom; D.u_apply = q.u_apply;
-        D.diag = q.diag ? q.diag : b.diags + i;
-        D.du = b.du + du_off; D.S = b.S + k_off; D.w = b.w + k_off; D.u_upd = b.u_upd + u_off;
+        D.diag = q.diag && !own_diags ? q.diag : b.diags + i;
+        D.du = b.du + du_off; D.S = b.S + k_off; D.u_upd = b.u_upd + u_off;
+        D.W = (K + tile - 1) / tile * cfg.block / 64;
+        D.stat = b.stat + st_off;
         du_off += 4 * (size_t)N * ld; k_off += ld; u_off += 4 * (size_t)N; row += 4 * N;
+        st_off += (size_t)D.W;
         // cost of one tile: N steps of dynamics plus this lane's share of the obstacles
         const long long cost = (long long)N * (650 + 11 * ((q.M + lanes - 1) / lanes));
         for (int k0 = 0; k0 < K; k0 += tile) work.push_back({cost, i, k0});
@@ -136,14 +141,14 @@ size_t fill_plan(mppi_ctx* ctx, const mppi_request* reqs, int n, const BatchLaun
 // Copy the plan to the device on `s` (waiting first for the previous copy out of the
 // pinned buffer, which this call overwrites).
 mppi_status stage_plan(mppi_ctx* ctx, const mppi_request* reqs, int n, const BatchLaunch& cfg,
-                       hipStream_t s)
+                       hipStream_t s, bool own_diags = false)
 {
     BatchState& b = ctx->batch;
     if (b.staged_pending) {
         HIP_TRY(ctx, hipEventSynchronize(b.staged));
         b.staged_pending = false;
     }
-    const size_t bytes = fill_plan(ctx, reqs, n, cfg);
+    const size_t bytes = fill_plan(ctx, reqs, n, cfg, own_diags);
     HIP_TRY(ctx, hipMemcpyAsync(b.plan_dev, b.plan_host, bytes, hipMemcpyHostToDevice, s));
     HIP_TRY(ctx, hipEventRecord(b.staged, s));
     b.staged_pending = true;
@@ -182,7 +187,7 @@ void free_batch(mppi_ctx* ctx)
     destroy_graph(b);
     if (b.staged_pending && b.staged) (void)hipEventSynchronize(b.staged);
     (void)hipFree(b.plan_dev); (void)hipFree(b.diags); (void)hipFree(b.du); (void)hipFree(b.S);
-    (void)hipFree(b.w); (void)hipFree(b.u_upd);
+    (void)hipFree(b.stat); (void)hipFree(b.u_upd);
     if (b.plan_host) (void)hipHostFree(b.plan_host);
     if (b.staged) (void)hipEventDestroy(b.staged);
     if (b.capture_stream) (void)hipStreamDestroy(b.capture_stream);
@@ -222,7 +227,7 @@ mppi_status batch_reserve_raw(mppi_ctx* ctx, int n, size_t du, size_t k, size_t 
               hipMalloc(&b.diags, sizeof(mppi_diag) * grow.n) == hipSuccess &&
               hipMalloc(&b.du, sizeof(float) * grow.du) == hipSuccess &&
               hipMalloc(&b.S, sizeof(float) * grow.k) == hipSuccess &&
-              hipMalloc(&b.w, sizeof(float) * grow.k) == hipSuccess &&
+              hipMalloc(&b.stat, sizeof(WaveStat) * (grow.k / 8 + 4 * (size_t)grow.n)) == hipSuccess &&
               hipMalloc(&b.u_upd, sizeof(float) * grow.u) == hipSuccess &&
               hipEventCreateWithFlags(&b.staged, hipEventDisableTiming) == hipSuccess &&
               hipStreamCreateWithFlags(&b.capture_stream, hipStreamNonBlocking) == hipSuccess;
@@ -233,6 +238,7 @@ mppi_status batch_reserve_raw(mppi_ctx* ctx, int n, size_t du, size_t k, size_t 
     }
     b.n_cap = grow.n; b.M_cap = grow.M_max; b.du_cap = grow.du; b.k_cap = grow.k; b.u_cap = grow.u;
     b.items_cap = grow.items_min_tile; b.plan_bytes = L.bytes;
+    b.stat_cap = grow.k / 8 + 4 * (size_t)grow.n;
     return MPPI_OK;
 }
 
@@ -273,8 +279,8 @@ mppi_status mppi_batch_update(mppi_ctx* ctx, void* stream, const mppi_request* r
         return MPPI_OK;
     }
     if (!b.use_graph) {
-        HIP_TRY(ctx, launch_batch(dev_header(b), dev_descs(b), dev_items(b), b.n_cap, ctx->cu_count,
-                                  lds_bytes(b), b.cfg, s));
+        HIP_TRY(ctx, launch_batch(dev_header(b), dev_descs(b), dev_items(b), b.n_cap,
+                                  ctx->cu_count, lds_bytes(b), b.cfg, s));
         return MPPI_OK;
     }
     const auto key = std::make_tuple(b.cfg.block, b.cfg.lanes, b.cfg.unroll, b.cfg.blocks_per_cu,
@@ -345,7 +351,7 @@ mppi_status mppi_batch_autotune(mppi_ctx* ctx, void* stream, const mppi_request*
     float best_ms = 1e30f;
     mppi_status result = MPPI_OK;
     for (const BatchLaunch& c : candidates) {
-        if ((result = stage_plan(ctx, reqs, n, c, s)) != MPPI_OK) break;
+        if ((result = stage_plan(ctx, reqs, n, c, s, true)) != MPPI_OK) break;
         hipError_t e = launch_batch_rollout(dev_header(b), dev_descs(b), dev_items(b),
                                             ctx->cu_count, lds_bytes(b), c, s);   // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, s);

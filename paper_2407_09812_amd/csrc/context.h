@@ -25,7 +25,8 @@ struct BatchState {
     mppi_diag* diags = nullptr;      // [n_cap], used when a request passes no diag
     float* du = nullptr;
     float* S = nullptr;
-    float* w = nullptr;
+    WaveStat* stat = nullptr;        // [stat_cap] weight statistics of the rollout waves
+    size_t stat_cap = 0;
     float* u_upd = nullptr;
     hipEvent_t staged = nullptr;     // the last H2D copy out of plan_host has completed
     bool staged_pending = false;
@@ -47,6 +48,17 @@ struct mppi_ctx {
     float* w = nullptr;         // [ld]
     float* u_upd = nullptr;     // [N_cap][4]
     mppi_diag* diag = nullptr;  // 1
+    // weight statistics per rollout wave; single pass: partial sums [W_cap][4 N]
+    int W_cap = 0;
+    mppi::WaveStat* wstat = nullptr;
+    float* part = nullptr;
+    unsigned int* rho_run = nullptr;   // running minimum of the waves (+inf between updates)
+    int* list_idx = nullptr;           // waves contributing partial sums [W_cap]
+    float* list_s = nullptr;           //   and their factors
+    int* list_n = nullptr;
+    // arrival counters of the rollout and weighted-sum launches (0 between launches)
+    unsigned int* counters = nullptr;
+    float* u_tmp = nullptr;            // autotuning's advanced sequence and applied control
     std::map<std::tuple<int, int, int>, mppi::LaunchConfig> tuned;   // size class -> shape
     std::string last_error;
     // profiling: 5 events per update bracket rollout, weights, sum, apply

@@ -32,13 +32,53 @@ struct RolloutArgs {
 // Rollout launch shape: `lanes` consecutive lanes per sample (the obstacle tests are
 // divided among them), `block` threads per workgroup, obstacle loop unrolled `unroll`.
 struct LaunchConfig {
-    int block;    // 64, 128, 256
-    int lanes;    // 1, 2, 4, 8
-    int unroll;   // 1, 4
+    int block;      // 64, 128, 256
+    int lanes;      // 1, 2, 4, 8
+    int unroll;     // 1, 4
+    int fused = 0;  // 1: single pass (per-wave partial sums), 0: stored delta_u
 };
 
 bool valid_config(const LaunchConfig& c);
-hipError_t launch_rollout(const RolloutArgs& a, const LaunchConfig& cfg, hipStream_t stream);
+// What the rollout launch of a full update does after the rollouts: per-wave weight
+// statistics, reduced into diag by the last workgroup (and, in the single pass, the
+// per-wave partial sums and the list of contributing waves).
+struct UpdateTail {
+    float lambda = 1.0f;
+    WaveStat* stat = nullptr;          // [W]; nullptr: rollouts only (stage call)
+    unsigned int* counter = nullptr;   // arrival counter, 0 between launches
+    mppi_diag* diag = nullptr;
+    float* part = nullptr;             // single pass: [W][4 N]
+    unsigned int* rho_run = nullptr;   // single pass: running minimum, +inf between launches
+    int* list_idx = nullptr;           // single pass: contributing waves [W]
+    float* list_s = nullptr;           //   and their factors exp(-(rho_w - rho) / lambda)
+    int* list_n = nullptr;
+};
+
+// Apply and advance, done by the last workgroup of the weighted-sum launch.
+struct ApplyArgs {
+    ModelParams P;
+    const float* x_hat;
+    float* u_nom;
+    float* u_apply;
+    int N;
+    float4 u_init;
+    float alpha;
+};
+
+// Rollouts (with tail: and the full update's weight statistics).
+hipError_t launch_rollout(const RolloutArgs& a, const LaunchConfig& cfg, hipStream_t stream,
+                          const UpdateTail* tail = nullptr);
+// Waves of a rollout launch of this shape (one statistics record each).
+int rollout_waves(int K, const LaunchConfig& c);
+hipError_t launch_rollout_fused(const RolloutArgs& a, const LaunchConfig& c, const UpdateTail& tail,
+                                hipStream_t stream);
+hipError_t launch_update_sum(const float* S, const float* du, int K, int N, int ld, float lambda,
+                             const float* u_in, float* u_upd, const mppi_diag* diag,
+                             const ApplyArgs& ap, unsigned int* counter, hipStream_t stream);
+hipError_t launch_merge_sum(const float* part, int N, const int* list_idx, const float* list_s,
+                            const int* list_n, const float* u_in, float* u_upd,
+                            const mppi_diag* diag, const ApplyArgs& ap, unsigned int* counter,
+                            hipStream_t stream);
 hipError_t launch_weights(const float* S, int K, float lambda, float* w, mppi_diag* diag, int lanes,
                           hipStream_t stream);
 hipError_t launch_weighted_sum(const float* w, const float* du, int K, int N, int ld,

@@ -7,6 +7,12 @@
 //                       sum of exp(-(S - rho)/lambda), normalisation   Eq. (4)
 //   weighted_sum_kernel one workgroup per (j, d) row of delta_u [N][4][ld]:
 //                       coalesced float4 GEMV against the weights       Eq. (5)
+//   update_sum_kernel   the full update's weighted sum, weights formed on the fly
+//                       from the costs and the statistics the rollout launch reduced;
+//                       its last workgroup applies and advances
+//   rollout_fused_kernel, merge_sum_kernel   the single pass: per-wave partial sums
+//                       with regenerated noise instead of stored delta_u, then their
+//                       rescaled sum (and apply)
 //   apply_shift_kernel  u_apply and the advanced warm start   Algorithm 1, Sec. IV-B
 //   plant_kernel        noise-free model steps (plant, delay prediction)  Sec. IV-E
 //   noise_kernel, philox_kernel   the rollout's noise on its own (checks)
@@ -17,18 +23,79 @@
 
 namespace mppi {
 
+// Rollouts; with stat (a full update), each wave also writes its weight statistics
+// and the last workgroup reduces them into diag.
 template <int L, int U, bool kLag, bool kDump>
 __global__ __launch_bounds__(256) void rollout_kernel(
     RolloutParams a, const float* __restrict__ x_hat, const float* __restrict__ x_ref,
     const mppi_obstacle* __restrict__ obs, const float* __restrict__ u_nom,
-    float* __restrict__ du_out, float* __restrict__ S_out, float* __restrict__ states)
+    float* __restrict__ du_out, float* __restrict__ S_out, float* __restrict__ states,
+    UpdateTail tail)
 {
     extern __shared__ float4 obs_lds[];   // obstacle_lds_bytes(M)
     stage_obstacles(obs_lds, obs, a.M, x_hat[0], x_hat[1], x_hat[2], a.cp.margin);
     __syncthreads();
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    rollout_sample<L, U, kLag, kDump>(a, x_hat, x_ref, u_nom, du_out, S_out, states, obs_lds, g / L,
-                                      g % L);
+    const int k = g / L, q = g % L;
+    const float S = rollout_sample<L, U, kLag, kDump>(a, x_hat, x_ref, u_nom, du_out, S_out, states,
+                                                      obs_lds, k, q);
+    if (tail.stat == nullptr) return;                       // launch-uniform
+    write_wave_stat(tail.stat + (g >> 6), wave_sums(S, k, q, k < a.K, tail.lambda), false);
+    if (last_to_arrive(tail.counter))
+        reduce_wave_stats(tail.stat, (int)(gridDim.x * blockDim.x >> 6), tail.lambda, L, tail.diag,
+                          nullptr, nullptr, nullptr);
+}
+
+// Single pass: rollouts, per-wave statistics and partial sums; the last workgroup
+// reduces the statistics into diag and the list of contributing waves.
+template <int L, int U, bool kLag>
+__global__ __launch_bounds__(256) void rollout_fused_kernel(
+    RolloutParams a, const float* __restrict__ x_hat, const float* __restrict__ x_ref,
+    const mppi_obstacle* __restrict__ obs, const float* __restrict__ u_nom,
+    float* __restrict__ S_out, UpdateTail tail)
+{
+    extern __shared__ float4 obs_lds[];   // obstacle_lds_bytes(M)
+    stage_obstacles(obs_lds, obs, a.M, x_hat[0], x_hat[1], x_hat[2], a.cp.margin);
+    __syncthreads();
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = g / L, q = g % L;
+    const float S = rollout_sample<L, U, kLag, false, false>(a, x_hat, x_ref, u_nom, nullptr, S_out,
+                                                             nullptr, obs_lds, k, q);
+    const int w = g >> 6;
+    fused_wave_partials<L>(a, tail.lambda, wave_sums(S, k, q, k < a.K, tail.lambda), k, q,
+                           tail.stat + w, tail.part + (size_t)w * 4 * a.N, tail.rho_run);
+    if (last_to_arrive(tail.counter)) {
+        reduce_wave_stats(tail.stat, (int)(gridDim.x * blockDim.x >> 6), tail.lambda, L, tail.diag,
+                          tail.list_idx, tail.list_s, tail.list_n);
+        if (threadIdx.x == 0) *tail.rho_run = 0x7f800000u;   // every wave has published
+    }
+}
+
+// Weighted sum of the stored delta_u, one workgroup per row; the last workgroup
+// applies and advances (Eqs. (5), (12)-(15), Sec. IV-B).
+__global__ __launch_bounds__(kSumThreads) void update_sum_kernel(
+    const float* __restrict__ S, const float* __restrict__ du, int K, int ld, float lambda,
+    const float* __restrict__ u_in, float* __restrict__ u_upd, const mppi_diag* __restrict__ diag,
+    ApplyArgs ap, unsigned int* __restrict__ counter)
+{
+    update_sum_row(S, du, K, ld, lambda, u_in, u_upd, diag, blockIdx.x);
+    if (last_to_arrive(counter))
+        apply_shift_block(ap.P, ap.x_hat, u_upd, ap.u_nom, ap.u_apply, ap.N, ap.u_init, ap.alpha,
+                          diag);
+}
+
+// Single pass: the listed waves' partial sums, 64 columns per workgroup; the last
+// workgroup applies and advances.
+__global__ __launch_bounds__(kMergeThreads) void merge_sum_kernel(
+    const float* __restrict__ part, int N, const int* __restrict__ list_idx,
+    const float* __restrict__ list_s, const int* __restrict__ list_n, const float* __restrict__ u_in,
+    float* __restrict__ u_upd, const mppi_diag* __restrict__ diag, ApplyArgs ap,
+    unsigned int* __restrict__ counter)
+{
+    merge_sum_cols(part, N, list_idx, list_s, list_n, u_in, u_upd, diag, blockIdx.x * 64);
+    if (last_to_arrive(counter))
+        apply_shift_block(ap.P, ap.x_hat, u_upd, ap.u_nom, ap.u_apply, ap.N, ap.u_init, ap.alpha,
+                          diag);
 }
 
 __global__ __launch_bounds__(kWeightsThreads) void weights_kernel(const float* __restrict__ S, int K,
@@ -91,39 +158,89 @@ bool valid_config(const LaunchConfig& c)
 {
     return (c.block == 64 || c.block == 128 || c.block == 256) &&
            (c.lanes == 1 || c.lanes == 2 || c.lanes == 4 || c.lanes == 8) &&
-           (c.unroll == 1 || c.unroll == 4);
+           (c.unroll == 1 || c.unroll == 4) && (c.fused == 0 || c.fused == 1);
+}
+
+int rollout_waves(int K, const LaunchConfig& c)
+{
+    const size_t threads = (size_t)K * c.lanes;
+    const size_t grid = (threads + c.block - 1) / c.block;
+    return (int)(grid * c.block / 64);
 }
 
 template <int L, int U>
-static hipError_t launch_rollout_lu(const RolloutArgs& a, int block, hipStream_t stream)
+static hipError_t launch_rollout_lu(const RolloutArgs& a, int block, const UpdateTail& tail,
+                                    bool fused, hipStream_t stream)
 {
     const size_t threads = (size_t)a.K * L;
     const int grid = (int)((threads + block - 1) / block);
     const size_t lds = obstacle_lds_bytes(a.M);
     const RolloutParams p{a.mp, a.cp, a.np, a.M, a.K, a.N, a.ld, a.obs_tests};
-    auto kernel = a.mp.lag ? (a.states ? rollout_kernel<L, U, true, true> : rollout_kernel<L, U, true, false>)
-                           : (a.states ? rollout_kernel<L, U, false, true> : rollout_kernel<L, U, false, false>);
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), lds, stream, p, a.x_hat, a.x_ref, a.obs,
-                       a.u_nom, a.du, a.S, a.states);
+    if (fused) {
+        auto kernel = a.mp.lag ? rollout_fused_kernel<L, U, true> : rollout_fused_kernel<L, U, false>;
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), lds, stream, p, a.x_hat, a.x_ref, a.obs,
+                           a.u_nom, a.S, tail);
+    } else {
+        auto kernel = a.mp.lag ? (a.states ? rollout_kernel<L, U, true, true> : rollout_kernel<L, U, true, false>)
+                               : (a.states ? rollout_kernel<L, U, false, true> : rollout_kernel<L, U, false, false>);
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), lds, stream, p, a.x_hat, a.x_ref, a.obs,
+                           a.u_nom, a.du, a.S, a.states, tail);
+    }
     return hipGetLastError();
 }
 
 template <int L>
-static hipError_t launch_rollout_l(const RolloutArgs& a, const LaunchConfig& c, hipStream_t stream)
+static hipError_t launch_rollout_l(const RolloutArgs& a, const LaunchConfig& c, const UpdateTail& tail,
+                                   bool fused, hipStream_t stream)
 {
-    return c.unroll == 4 ? launch_rollout_lu<L, 4>(a, c.block, stream)
-                         : launch_rollout_lu<L, 1>(a, c.block, stream);
+    return c.unroll == 4 ? launch_rollout_lu<L, 4>(a, c.block, tail, fused, stream)
+                         : launch_rollout_lu<L, 1>(a, c.block, tail, fused, stream);
 }
 
-hipError_t launch_rollout(const RolloutArgs& a, const LaunchConfig& c, hipStream_t stream)
+static hipError_t launch_rollout_any(const RolloutArgs& a, const LaunchConfig& c,
+                                     const UpdateTail& tail, bool fused, hipStream_t stream)
 {
     if (!valid_config(c)) return hipErrorInvalidValue;
     switch (c.lanes) {
-    case 1: return launch_rollout_l<1>(a, c, stream);
-    case 2: return launch_rollout_l<2>(a, c, stream);
-    case 4: return launch_rollout_l<4>(a, c, stream);
-    default: return launch_rollout_l<8>(a, c, stream);
+    case 1: return launch_rollout_l<1>(a, c, tail, fused, stream);
+    case 2: return launch_rollout_l<2>(a, c, tail, fused, stream);
+    case 4: return launch_rollout_l<4>(a, c, tail, fused, stream);
+    default: return launch_rollout_l<8>(a, c, tail, fused, stream);
     }
+}
+
+hipError_t launch_rollout(const RolloutArgs& a, const LaunchConfig& c, hipStream_t stream,
+                          const UpdateTail* tail)
+{
+    UpdateTail none{};
+    return launch_rollout_any(a, c, tail ? *tail : none, false, stream);
+}
+
+hipError_t launch_rollout_fused(const RolloutArgs& a, const LaunchConfig& c, const UpdateTail& tail,
+                                hipStream_t stream)
+{
+    if (!tail.stat || !tail.part || !tail.rho_run || !tail.list_idx) return hipErrorInvalidValue;
+    return launch_rollout_any(a, c, tail, true, stream);
+}
+
+hipError_t launch_update_sum(const float* S, const float* du, int K, int N, int ld, float lambda,
+                             const float* u_in, float* u_upd, const mppi_diag* diag,
+                             const ApplyArgs& ap, unsigned int* counter, hipStream_t stream)
+{
+    hipLaunchKernelGGL(update_sum_kernel, dim3(4 * N), dim3(kSumThreads), 0, stream, S, du, K, ld,
+                       lambda, u_in, u_upd, diag, ap, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_sum(const float* part, int N, const int* list_idx, const float* list_s,
+                            const int* list_n, const float* u_in, float* u_upd,
+                            const mppi_diag* diag, const ApplyArgs& ap, unsigned int* counter,
+                            hipStream_t stream)
+{
+    const int grid = (4 * N + 63) / 64;
+    hipLaunchKernelGGL(merge_sum_kernel, dim3(grid), dim3(kMergeThreads), 0, stream, part, N,
+                       list_idx, list_s, list_n, u_in, u_upd, diag, ap, counter);
+    return hipGetLastError();
 }
 
 hipError_t launch_weights(const float* S, int K, float lambda, float* w, mppi_diag* diag, int lanes,

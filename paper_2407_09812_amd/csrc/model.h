@@ -66,6 +66,21 @@ constexpr int kWeightsThreads = 1024;   // one workgroup computes one instance's
 constexpr int kSumThreads = 256;        // one workgroup reduces one delta_u row
 
 // 17 state values held in registers.
+// Per-wave partial results of the single-pass update (written by the rollout
+// kernel's epilogue, read by the merge).
+struct WaveStat {
+    float rho;            // minimum finite cost of the wave (+inf if none)
+    float eta_s, eta_c;   // compensated sum of exp(-(S_k - rho) / lambda)
+    float q;              // sum of their squares
+    int argmin;           // first sample attaining rho (-1 if none)
+    int n;                // finite costs
+    int skipped;          // 1: every weight underflows, no partial sums written
+    int pad;
+};
+
+constexpr int kMergeThreads = 256;   // single-pass sum workgroup: 64 columns x 4 waves
+constexpr float kSkipLog2 = 160.0f;  // waves whose weights are all below 2^-160 skip
+
 struct State {
     float px, py, pz;
     float qw, qx, qy, qz;

@@ -76,12 +76,13 @@ __device__ __forceinline__ void stage_obstacles(float4* blk, const mppi_obstacle
 
 // Rollout of sample k by lane q of its L lanes.  The L lanes integrate the same
 // sample (identical instructions and operands, hence identical trajectories) and
-// divide its obstacle tests; lane q = 0 of a valid sample writes delta_u [N][4][ld],
-// S [K] and the optional trajectory dump [N+1][17][ld] (world-frame positions).
-// Lanes past the last sample run a copy of sample K-1 without writing, so that
-// every lane of the wave takes part in the wave-wide obstacle culling.
-template <int L, int U, bool kLag, bool kDump>
-__device__ __forceinline__ void rollout_sample(const RolloutParams& a, const float* __restrict__ x_hat,
+// divide its obstacle tests; lane q = 0 of a valid sample writes delta_u [N][4][ld]
+// (unless kStoreDu is false), S [K] and the optional trajectory dump [N+1][17][ld]
+// (world-frame positions).  Lanes past the last sample run a copy of sample K-1
+// without writing, so that every lane of the wave takes part in the wave-wide
+// obstacle culling.  Returns the sample's cost (on all L lanes).
+template <int L, int U, bool kLag, bool kDump, bool kStoreDu = true>
+__device__ __forceinline__ float rollout_sample(const RolloutParams& a, const float* __restrict__ x_hat,
                                                const float* __restrict__ x_ref,
                                                const float* __restrict__ u_nom,
                                                float* __restrict__ du_out, float* __restrict__ S_out,
@@ -117,7 +118,7 @@ __device__ __forceinline__ void rollout_sample(const RolloutParams& a, const flo
     for (int j = 0; j < a.N; ++j) {
         float du[4], u[4];
         draw_noise(a.np, (uint32_t)k, (uint32_t)j, du);
-        if (writer) {
+        if (kStoreDu && writer) {
             float* dst = du_out + (size_t)(4 * j) * ld + k;
 #pragma unroll
             for (int d = 0; d < 4; ++d) dst[(size_t)d * ld] = du[d];
@@ -160,6 +161,7 @@ __device__ __forceinline__ void rollout_sample(const RolloutParams& a, const flo
         const unsigned long long samples = __popcll(__ballot(writer));
         if (__lane_id() == 0) atomicAdd(a.obs_tests, samples * (unsigned long long)tested);
     }
+    return S.s;
 }
 
 // ---------------------------------------------------------------------------
@@ -333,6 +335,348 @@ __device__ __forceinline__ void feasible_input(const ModelParams& P, const float
         float wc = fmaf((tau[i] - gyr[i]) * P.J_inv[i], P.dt, x[10 + i]);
         if (lim[i] > 0.0f) wc = clampf(wc, -lim[i], lim[i]);
         out[1 + i] = wc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The update in two launches.  The rollout launch ends with per-wave statistics of
+// the weights (Eq. (4) relative to each wave's minimum), which its last workgroup
+// reduces into the update's rho, eta and diagnostics; the second launch forms the
+// weighted sum (Eq. (5)) and its last workgroup applies and advances the warm start.
+// The weighted sum reads either the stored delta_u (a GEMV) or, in the single pass,
+// per-wave partial sums that the rollout waves formed from regenerated noise, so that
+// delta_u never goes to memory.
+// ---------------------------------------------------------------------------
+
+// Eq. (4) over one wave, relative to its own minimum.
+struct WaveSums {
+    float rho;      // minimum finite cost of the wave's valid samples (+inf if none)
+    int argmin;     // first sample attaining it (INT_MAX if none)
+    int n;          // finite costs, each sample counted once
+    float es, ec;   // compensated sum of e_k = exp(-(S_k - rho) / lambda)
+    float q2;       // sum of e_k^2
+    float e;        // this lane's e_k (0 for an invalid lane or a non-finite cost)
+};
+
+// S: the lane's sample cost; k its sample, q its lane within the sample, valid = k < K.
+// Every lane of the wave calls it and gets the wave's sums.
+__device__ __forceinline__ WaveSums wave_sums(float S, int k, int q, bool valid, float lambda)
+{
+    WaveSums w;
+    const bool fin = valid && isfinite(S);
+    float mv = fin ? S : INFINITY;
+    int mi = fin ? k : INT_MAX;
+    int nf = (fin && q == 0) ? 1 : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const float v2 = __shfl_xor(mv, off);
+        const int i2 = __shfl_xor(mi, off);
+        argmin_merge(mv, mi, v2, i2);
+        nf += __shfl_xor(nf, off);
+    }
+    w.rho = mv; w.argmin = mi; w.n = nf;
+    const float scale = 1.44269504089f / lambda;
+    w.e = fin ? __builtin_amdgcn_exp2f((mv - S) * scale) : 0.0f;
+    float es = q == 0 ? w.e : 0.0f, ec = 0.0f, q2 = es * es;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const float s2 = __shfl_xor(es, off), c2 = __shfl_xor(ec, off);
+        twosum_merge(es, ec, s2, c2);
+        q2 += __shfl_xor(q2, off);
+    }
+    w.es = es; w.ec = ec; w.q2 = q2;
+    return w;
+}
+
+__device__ __forceinline__ void write_wave_stat(WaveStat* __restrict__ stat, const WaveSums& w,
+                                                bool skipped)
+{
+    if (__lane_id() == 0) {
+        WaveStat s;
+        s.rho = w.rho; s.eta_s = w.es; s.eta_c = w.ec; s.q = w.q2;
+        s.argmin = w.n > 0 ? w.argmin : -1; s.n = w.n; s.skipped = skipped ? 1 : 0; s.pad = 0;
+        *stat = s;
+    }
+}
+
+// Sum of v[0..15] over the lanes of the wave that share lane % L (the samples of the
+// wave, one lane per sample for each of the L lane positions), by a butterfly that
+// halves the values each lane carries at every exchange.  Afterwards a lane holds
+// R = 16 >> ST sums: v[m] is the total of value (m << ST) | ((lane >> log2 L) & (2^ST - 1)),
+// ST = min(4, 6 - log2 L); lanes whose bits above log2 L + ST are zero hold distinct
+// totals.
+template <int L>
+__device__ __forceinline__ void wave_sum16(float (&v)[16], int lane)
+{
+    constexpr int LB = L == 1 ? 0 : L == 2 ? 1 : L == 4 ? 2 : 3;
+    constexpr int BITS = 6 - LB;
+    constexpr int ST = BITS < 4 ? BITS : 4;
+#pragma unroll
+    for (int s = 0; s < ST; ++s) {
+        const int mask = 1 << (LB + s);
+        const bool hi = (lane & mask) != 0;
+#pragma unroll
+        for (int m = 0; m < (16 >> (s + 1)); ++m) {
+            const float keep = hi ? v[2 * m + 1] : v[2 * m];
+            const float send = hi ? v[2 * m] : v[2 * m + 1];
+            v[m] = keep + __shfl_xor(send, mask);
+        }
+    }
+#pragma unroll
+    for (int s = ST; s < BITS; ++s) v[0] += __shfl_xor(v[0], 1 << (LB + s));
+}
+
+// Single pass, per wave: P_w[4 j + d] = sum_k e_k delta_u_{k,j,d} (Eq. (5) before the
+// normalisation) with delta_u regenerated from the counter-based noise; lane q of a
+// sample regenerates the chunks of four steps c = r L + q, so the L lanes of a sample
+// share the regeneration.
+//
+// rho_run holds the bits of the smallest wave minimum published so far (costs are sums
+// of non-negative terms, so the bits order like the values).  A wave whose minimum lies
+// more than kSkipLog2 / (log2(e) / lambda) above it has every weight below
+// 2^-kSkipLog2 relative to the final minimum -- exactly zero in binary32, as in the
+// stored form -- and skips the regeneration (stat->skipped = 1).
+template <int L>
+__device__ __forceinline__ void fused_wave_partials(const RolloutParams& a, float lambda,
+                                                    const WaveSums& ws, int k, int q,
+                                                    WaveStat* __restrict__ stat,
+                                                    float* __restrict__ part,
+                                                    unsigned int* __restrict__ rho_run)
+{
+    const int lane = __lane_id();
+    const float scale = 1.44269504089f / lambda;
+    unsigned int seen = 0x7f800000u;            // +inf
+    if (lane == 0 && ws.n > 0) seen = atomicMin(rho_run, __float_as_uint(ws.rho + 0.0f));
+    const float best = fminf(ws.rho, __uint_as_float(__builtin_amdgcn_readfirstlane(seen)));
+    const bool skip = ws.n == 0 || (ws.rho - best) * scale > kSkipLog2;
+    write_wave_stat(stat, ws, skip);
+    if (skip) return;                           // wave-uniform
+
+    constexpr int LB = L == 1 ? 0 : L == 2 ? 1 : L == 4 ? 2 : 3;
+    constexpr int ST = 6 - LB < 4 ? 6 - LB : 4;
+    const int nchunks = (a.N + 3) >> 2, n4 = 4 * a.N;
+    const int idx_bits = (lane >> LB) & ((1 << ST) - 1);
+    const bool store = (lane >> (LB + ST)) == 0;
+    const float e = ws.e;
+    for (int r = 0; r * L < nchunks; ++r) {
+        const int c = r * L + q;
+        float v[16];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int j = 4 * c + s;
+            float du[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (e != 0.0f && j < a.N) draw_noise(a.np, (uint32_t)k, (uint32_t)j, du);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) v[4 * s + d] = e * du[d];
+        }
+        wave_sum16<L>(v, lane);
+        if (store) {
+#pragma unroll
+            for (int m = 0; m < (16 >> ST); ++m) {
+                const int elem = 16 * c + ((m << ST) | idx_bits);
+                if (elem < n4) part[elem] = v[m];
+            }
+        }
+    }
+}
+
+// Arrival counter: every thread of a workgroup calls it after the workgroup's writes;
+// true (on all its threads) for the workgroup that brings the count to `total`, which
+// then sees the writes of every workgroup counted before it.  With reset, that
+// workgroup also sets the counter back to 0.
+__device__ __forceinline__ bool last_of(unsigned int* counter, unsigned int total, bool reset)
+{
+    __shared__ int s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();                                    // release this workgroup's writes
+        const bool last = atomicAdd(counter, 1u) == total - 1;
+        if (last && reset) atomicExch(counter, 0u);
+        s_last = last ? 1 : 0;
+    }
+    __syncthreads();
+    const bool last = s_last != 0;
+    if (last) __threadfence();                              // acquire the others' writes
+    return last;
+}
+
+// The workgroup of a launch that arrives last (the counter returns to 0 for the next).
+__device__ __forceinline__ bool last_to_arrive(unsigned int* counter)
+{
+    return last_of(counter, gridDim.x * gridDim.y * gridDim.z, true);
+}
+
+// Reduce the per-wave statistics stat[0..W) of one update: rho = min rho_w with its
+// first sample, n_finite, and with s_w = exp(-(rho_w - rho) / lambda), eta = sum_w s_w
+// eta_w and sum w_k^2 = sum_w s_w^2 q_w / eta^2 (binary64 sums), written to diag
+// (Eq. (4); ess = 1 / sum w_k^2).  With list_idx, also the waves with s_w > 0 that
+// formed partial sums, in index order, with their s_w (single pass).  Done by the
+// first wave of the calling workgroup in a fixed order (lane l takes l, l + 64, ...),
+// so the result does not depend on the workgroup size; eight records are loaded at a
+// time per lane.
+__device__ inline void reduce_wave_stats(const WaveStat* __restrict__ stat, int W, float lambda,
+                                         int lanes, mppi_diag* __restrict__ diag,
+                                         int* __restrict__ list_idx, float* __restrict__ list_s,
+                                         int* __restrict__ list_n)
+{
+    if (threadIdx.x >= 64) return;
+    constexpr int kBatch = 8;
+    const int lane = threadIdx.x;
+    const float scale = 1.44269504089f / lambda;
+
+    float mv = INFINITY;
+    int mi = INT_MAX, nf = 0;
+    for (int w0 = lane; w0 < W; w0 += 64 * kBatch) {
+        WaveStat r[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int w = w0 + 64 * u;
+            if (w < W) r[u] = stat[w]; else r[u].n = 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            nf += r[u].n;
+            if (r[u].n > 0) argmin_merge(mv, mi, r[u].rho, r[u].argmin);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const float v2 = __shfl_xor(mv, off);
+        const int i2 = __shfl_xor(mi, off);
+        argmin_merge(mv, mi, v2, i2);
+        nf += __shfl_xor(nf, off);
+    }
+    const float rho = mv;
+    if (lane == 0) {
+        diag->rho = rho; diag->argmin = nf > 0 ? mi : -1; diag->n_finite = nf; diag->lanes = lanes;
+        if (nf == 0) {
+            diag->eta = 0.0f; diag->ess = 0.0f; diag->status = MPPI_E_ALL_NONFINITE;
+            if (list_n) *list_n = 0;
+        }
+    }
+    if (nf == 0) return;
+
+    double eta = 0.0, q2 = 0.0;
+    int base = 0;
+    for (int c0 = 0; c0 < W; c0 += 64 * kBatch) {
+        WaveStat r[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int w = c0 + 64 * u + lane;
+            if (w < W) r[u] = stat[w]; else r[u].n = 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const float f = r[u].n > 0 ? __builtin_amdgcn_exp2f((rho - r[u].rho) * scale) : 0.0f;
+            if (r[u].n > 0) {
+                eta += (double)f * ((double)r[u].eta_s + (double)r[u].eta_c);
+                q2 += (double)f * (double)f * (double)r[u].q;
+            }
+            if (list_idx) {                    // contributing waves, in index order
+                const bool in = f != 0.0f && !r[u].skipped;
+                const unsigned long long m = __ballot(in);
+                const int at = base + __popcll(m & ((1ull << lane) - 1ull));
+                if (in) { list_idx[at] = c0 + 64 * u + lane; list_s[at] = f; }
+                base += __popcll(m);
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        eta += __shfl_xor(eta, off);
+        q2 += __shfl_xor(q2, off);
+    }
+    if (lane == 0) {
+        diag->eta = (float)eta; diag->ess = (float)(eta * eta / q2); diag->status = MPPI_OK;
+        if (list_n) *list_n = base;
+    }
+}
+
+// Stored form, one workgroup of kSumThreads per row 4 j + d of delta_u [N][4][ld]:
+// u_out[row] = u_in[row] + sum_k e_k delta_u[row][k] / eta with e_k = exp(-(S_k - rho)
+// / lambda) (0 for non-finite costs), rho and eta from diag; u_out = u_in when every
+// cost is non-finite.
+__device__ __forceinline__ void update_sum_row(const float* __restrict__ S, const float* __restrict__ du,
+                                               int K, int ld, float lambda,
+                                               const float* __restrict__ u_in, float* __restrict__ u_out,
+                                               const mppi_diag* __restrict__ diag, int row)
+{
+    __shared__ float sh[kSumThreads / 64];
+    const int tid = threadIdx.x;
+    const float rho = diag->rho, eta = diag->eta;
+    const bool ok = diag->status == MPPI_OK;
+    if (!ok) {
+        if (tid == 0) u_out[row] = u_in[row];
+        return;
+    }
+    const float scale = 1.44269504089f / lambda;
+    const float* src = du + (size_t)row * ld;
+    float acc = 0.0f;
+    auto wt = [&](float s) { return isfinite(s) ? __builtin_amdgcn_exp2f((rho - s) * scale) : 0.0f; };
+    if ((ld & 3) == 0) {
+        const int K4 = K >> 2;
+        const float4* s4 = reinterpret_cast<const float4*>(src);
+        const float4* c4 = reinterpret_cast<const float4*>(S);
+        for (int i = tid; i < K4; i += blockDim.x) {
+            const float4 a = s4[i], c = c4[i];
+            acc = fmaf(a.x, wt(c.x), acc);
+            acc = fmaf(a.y, wt(c.y), acc);
+            acc = fmaf(a.z, wt(c.z), acc);
+            acc = fmaf(a.w, wt(c.w), acc);
+        }
+        for (int k = 4 * K4 + tid; k < K; k += blockDim.x) acc = fmaf(src[k], wt(S[k]), acc);
+    } else {
+        for (int k = tid; k < K; k += blockDim.x) acc = fmaf(src[k], wt(S[k]), acc);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((tid & 63) == 0) sh[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        float t = 0.0f;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+        u_out[row] = u_in[row] + t / eta;
+    }
+}
+
+// Single pass, one workgroup of kMergeThreads = 64 columns x 4 waves: u_out[col] =
+// u_in[col] + sum over the listed waves of s_w P_w[col] / eta (binary64), the waves
+// of the list divided among the workgroup's waves.
+__device__ __forceinline__ void merge_sum_cols(const float* __restrict__ part, int N,
+                                               const int* __restrict__ list_idx,
+                                               const float* __restrict__ list_s,
+                                               const int* __restrict__ list_n,
+                                               const float* __restrict__ u_in, float* __restrict__ u_out,
+                                               const mppi_diag* __restrict__ diag, int col0)
+{
+    __shared__ double sh[kMergeThreads];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+    const int col = col0 + lane;
+    const int n4 = 4 * N;
+    const bool ok = diag->status == MPPI_OK;
+    double acc = 0.0;
+    if (ok && col < n4) {
+        const int n = *list_n;
+        const size_t ldp = (size_t)n4;
+        int t = wv;
+        for (; t + 3 * nw < n; t += 4 * nw) {              // four independent loads in flight
+            const float p0 = part[(size_t)list_idx[t] * ldp + col];
+            const float p1 = part[(size_t)list_idx[t + nw] * ldp + col];
+            const float p2 = part[(size_t)list_idx[t + 2 * nw] * ldp + col];
+            const float p3 = part[(size_t)list_idx[t + 3 * nw] * ldp + col];
+            acc += (double)list_s[t] * p0;
+            acc += (double)list_s[t + nw] * p1;
+            acc += (double)list_s[t + 2 * nw] * p2;
+            acc += (double)list_s[t + 3 * nw] * p3;
+        }
+        for (; t < n; t += nw) acc += (double)list_s[t] * part[(size_t)list_idx[t] * ldp + col];
+    }
+    sh[tid] = acc;
+    __syncthreads();
+    if (wv == 0 && col < n4) {
+        double tot = 0.0;
+        for (int w = 0; w < nw; ++w) tot += sh[w * 64 + lane];
+        u_out[col] = ok ? u_in[col] + (float)(tot / (double)diag->eta) : u_in[col];
     }
 }
 
