@@ -93,15 +93,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(K, N, M):
+def measured_traffic(K, N, M, launch):
     """HBM bytes per rollout launch from the committed rocprofv3 PMC summary, if it was
-    taken on the current kernel source; else None."""
+    taken on the current kernel source, this workload and this launch shape; else
+    None."""
     path = os.path.join(ROOT, "profiles", "rollout_c2_pmc_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("workload") != [K, N, M]:
+    if (rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("workload") != [K, N, M]
+            or rec.get("launch") != launch):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -167,7 +169,11 @@ def run(args):
     lib.mppi_reserve(ctx, K, N, M)
     stream = torch.cuda.current_stream()
     solves = [sc.solve(t) for t in range(total)]
-    if args.autotune:
+    if args.launch:
+        blk, lanes, unroll, fused = (int(v) for v in args.launch.split(","))
+        lib.mppi_set_config(ctx, K, N, M, blk, lanes, unroll, fused)
+        launch = lib.mppi_get_config(ctx, K, N, M)
+    elif args.autotune:
         launch = lib.mppi_autotune(ctx, sc.veh, sc.cost, solves[0], x_buf[0], refs[0], obs, M, u_nom,
                                    reps=3, stream=stream)
     else:
@@ -243,7 +249,7 @@ def run(args):
                        "mean": sum(lat) / len(lat)},
         "device_ms_per_update": {"rollout": rollout_ms, "sum_and_apply": sum_ms},
         "roofline": {
-            "kernel": "rollout_kernel",
+            "kernel": "rollout_fused_kernel" if launch.get("fused") else "rollout_kernel",
             "bound": "alu",
             "achieved": achieved / 1e12,
             "peak": PEAK_FP32_VECTOR / 1e12,
@@ -252,7 +258,7 @@ def run(args):
             "frac_of_unpacked_peak": achieved / PEAK_FP32_UNPACKED,
             "flop_per_launch": flop,
             "obstacle_tests_per_state": tests / (K * (N + 1)),
-            "traffic": measured_traffic(K, N, M),
+            "traffic": measured_traffic(K, N, M, launch),
         },
         "reduction": ({"kernel": "update_sum_kernel", "bound": "hbm",
                        "achieved": rbytes / (sum_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
@@ -507,6 +513,9 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=20,
                     help="batched updates of the 256-vehicle mix timed beside the plain line "
                          "(0 skips the batched leg)")
+    ap.add_argument("--launch", default="", metavar="BLOCK,LANES,UNROLL,FUSED",
+                    help="fixed launch shape of the single-vehicle leg instead of autotuning "
+                         "(profiling runs use it so that every pass runs the same kernels)")
     ap.add_argument("--variant", default="auto", choices=["auto", "stored", "fused"],
                     help="update variant of the single-vehicle leg: the autotuner's choice, "
                          "stored delta_u + weighted sum, or the single pass")

@@ -71,14 +71,18 @@ __global__ __launch_bounds__(256) void rollout_fused_kernel(
     }
 }
 
-// Weighted sum of the stored delta_u, one workgroup per row; the last workgroup
-// applies and advances (Eqs. (5), (12)-(15), Sec. IV-B).
+// Weighted sum of the stored delta_u, rows 4 j + d taken in turn by at most one
+// workgroup per CU (fewer arrivals to fence); the last workgroup applies and advances
+// (Eqs. (5), (12)-(15), Sec. IV-B).
 __global__ __launch_bounds__(kSumThreads) void update_sum_kernel(
     const float* __restrict__ S, const float* __restrict__ du, int K, int ld, float lambda,
     const float* __restrict__ u_in, float* __restrict__ u_upd, const mppi_diag* __restrict__ diag,
     ApplyArgs ap, unsigned int* __restrict__ counter)
 {
-    update_sum_row(S, du, K, ld, lambda, u_in, u_upd, diag, blockIdx.x);
+    for (int row = blockIdx.x; row < 4 * ap.N; row += gridDim.x) {
+        update_sum_row(S, du, K, ld, lambda, u_in, u_upd, diag, row);
+        __syncthreads();                     // the row's LDS partials are reused
+    }
     if (last_to_arrive(counter))
         apply_shift_block(ap.P, ap.x_hat, u_upd, ap.u_nom, ap.u_apply, ap.N, ap.u_init, ap.alpha,
                           diag);
@@ -225,9 +229,11 @@ hipError_t launch_rollout_fused(const RolloutArgs& a, const LaunchConfig& c, con
 
 hipError_t launch_update_sum(const float* S, const float* du, int K, int N, int ld, float lambda,
                              const float* u_in, float* u_upd, const mppi_diag* diag,
-                             const ApplyArgs& ap, unsigned int* counter, hipStream_t stream)
+                             const ApplyArgs& ap, unsigned int* counter, int sum_grid_cap,
+                             hipStream_t stream)
 {
-    hipLaunchKernelGGL(update_sum_kernel, dim3(4 * N), dim3(kSumThreads), 0, stream, S, du, K, ld,
+    const int grid = 4 * N < sum_grid_cap ? 4 * N : sum_grid_cap;
+    hipLaunchKernelGGL(update_sum_kernel, dim3(grid), dim3(kSumThreads), 0, stream, S, du, K, ld,
                        lambda, u_in, u_upd, diag, ap, counter);
     return hipGetLastError();
 }
