@@ -115,9 +115,23 @@ __device__ __forceinline__ float rollout_sample(const RolloutParams& a, const fl
           obstacle_cost<L, U>(a.cp, x.px, x.py, x.pz, obs_lds, a.M, q, tested));
 
     float up[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    // With L lanes per sample the noise is drawn round-robin: at steps j = 0, L, 2L, ...
+    // lane q draws step j + q, and each step's noise is read from its lane of the
+    // group -- one draw per L steps in the wave's instruction stream instead of one per
+    // step (the values are the same).
+    float nz[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    const int grp = (__lane_id() & ~(L - 1)) << 2;        // byte address of lane 0 of the group
     for (int j = 0; j < a.N; ++j) {
         float du[4], u[4];
-        draw_noise(a.np, (uint32_t)k, (uint32_t)j, du);
+        if (L == 1) {
+            draw_noise(a.np, (uint32_t)k, (uint32_t)j, du);
+        } else {
+            if (j % L == 0 && j + q < a.N) draw_noise(a.np, (uint32_t)k, (uint32_t)(j + q), nz);
+            const int src = grp | ((j % L) << 2);
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                du[d] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(nz[d])));
+        }
         if (kStoreDu && writer) {
             float* dst = du_out + (size_t)(4 * j) * ld + k;
 #pragma unroll
