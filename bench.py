@@ -170,16 +170,18 @@ def run(args):
     stream = torch.cuda.current_stream()
     solves = [sc.solve(t) for t in range(total)]
     if args.launch:
-        blk, lanes, unroll, fused = (int(v) for v in args.launch.split(","))
-        lib.mppi_set_config(ctx, K, N, M, blk, lanes, unroll, fused)
+        lib.mppi_set_config(ctx, K, N, M, *(int(v) for v in args.launch.split(",")))
         launch = lib.mppi_get_config(ctx, K, N, M)
     elif args.autotune:
         launch = lib.mppi_autotune(ctx, sc.veh, sc.cost, solves[0], x_buf[0], refs[0], obs, M, u_nom,
-                                   reps=3, stream=stream)
+                                   reps=8, stream=stream)
     else:
         launch = lib.mppi_get_config(ctx, K, N, M)
-    if args.variant != "auto":                   # force stored delta_u or the single pass
-        launch = dict(launch, fused=1 if args.variant == "fused" else 0)
+    if args.variant != "auto":                   # force one form of the update
+        launch = dict(launch, fused=1 if args.variant in ("fused", "pipe-fused") else 0,
+                      pipe=1 if args.variant in ("pipe", "pipe-fused") else 0)
+        if launch["pipe"]:
+            launch["block"] = 64
         lib.mppi_set_config(ctx, K, N, M, **launch)
     log(f"bench: rollout launch shape {launch}")
 
@@ -249,7 +251,8 @@ def run(args):
                        "mean": sum(lat) / len(lat)},
         "device_ms_per_update": {"rollout": rollout_ms, "sum_and_apply": sum_ms},
         "roofline": {
-            "kernel": "rollout_fused_kernel" if launch.get("fused") else "rollout_kernel",
+            "kernel": ("rollout_pipe_kernel" if launch.get("pipe") else
+                       "rollout_fused_kernel" if launch.get("fused") else "rollout_kernel"),
             "bound": "alu",
             "achieved": achieved / 1e12,
             "peak": PEAK_FP32_VECTOR / 1e12,
@@ -513,12 +516,14 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=20,
                     help="batched updates of the 256-vehicle mix timed beside the plain line "
                          "(0 skips the batched leg)")
-    ap.add_argument("--launch", default="", metavar="BLOCK,LANES,UNROLL,FUSED",
+    ap.add_argument("--launch", default="", metavar="BLOCK,LANES,UNROLL,FUSED[,PIPE]",
                     help="fixed launch shape of the single-vehicle leg instead of autotuning "
                          "(profiling runs use it so that every pass runs the same kernels)")
-    ap.add_argument("--variant", default="auto", choices=["auto", "stored", "fused"],
+    ap.add_argument("--variant", default="auto",
+                    choices=["auto", "stored", "fused", "pipe", "pipe-fused"],
                     help="update variant of the single-vehicle leg: the autotuner's choice, "
-                         "stored delta_u + weighted sum, or the single pass")
+                         "stored delta_u + weighted sum, the single pass, or the wave-specialised "
+                         "rollouts with either")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="use the library's default rollout launch shape")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,

@@ -67,7 +67,7 @@ class Diag(C.Structure):
 
 class LaunchConfig(C.Structure):
     _fields_ = [("block", C.c_int32), ("lanes", C.c_int32), ("unroll", C.c_int32),
-                ("fused", C.c_int32)]
+                ("fused", C.c_int32), ("pipe", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -359,11 +359,11 @@ def mppi_predict(ctx, veh, dt, delay, x_hat, u_hold, x_out, stream=None):
 def mppi_get_config(ctx, K, N, M) -> dict:
     c = LaunchConfig()
     ctx.check(_lib.mppi_get_config(ctx.handle, int(K), int(N), int(M), C.byref(c)), "mppi_get_config")
-    return dict(block=c.block, lanes=c.lanes, unroll=c.unroll, fused=c.fused)
+    return dict(block=c.block, lanes=c.lanes, unroll=c.unroll, fused=c.fused, pipe=c.pipe)
 
 
-def mppi_set_config(ctx, K, N, M, block, lanes, unroll, fused=0):
-    c = LaunchConfig(int(block), int(lanes), int(unroll), int(fused))
+def mppi_set_config(ctx, K, N, M, block, lanes, unroll, fused=0, pipe=0):
+    c = LaunchConfig(int(block), int(lanes), int(unroll), int(fused), int(pipe))
     ctx.check(_lib.mppi_set_config(ctx.handle, int(K), int(N), int(M), C.byref(c)), "mppi_set_config")
 
 
@@ -373,7 +373,8 @@ def mppi_autotune(ctx, veh, cst, slv, x_hat, x_ref, obs_dev, M, u_nom, reps=3, s
     ctx.check(_lib.mppi_autotune(ctx.handle, _stream(stream), C.byref(v), C.byref(c), C.byref(s),
                                  _ptr(x_hat), _ptr(x_ref), _ptr(obs_dev) if M > 0 else None,
                                  int(M), _ptr(u_nom), int(reps), C.byref(best)), "mppi_autotune")
-    return dict(block=best.block, lanes=best.lanes, unroll=best.unroll, fused=best.fused)
+    return dict(block=best.block, lanes=best.lanes, unroll=best.unroll, fused=best.fused,
+                pipe=best.pipe)
 
 
 def make_requests(items) -> C.Array:

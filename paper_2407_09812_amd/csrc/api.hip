@@ -256,17 +256,17 @@ hipError_t update_core(mppi_ctx* ctx, const RolloutArgs& a, const LaunchConfig& 
         tail.list_idx = ctx->list_idx;
         tail.list_s = ctx->list_s;
         tail.list_n = ctx->list_n;
-        e = launch_rollout_fused(a, cfg, tail, s);
+        e = cfg.pipe ? launch_rollout_pipe(a, cfg, s, &tail) : launch_rollout_fused(a, cfg, tail, s);
         if (e == hipSuccess) e = mark(1);
         if (e == hipSuccess)
             e = launch_merge_sum(ctx->part, a.N, ctx->list_idx, ctx->list_s, ctx->list_n, u_in,
                                  ctx->u_upd, dg, ap, ctx->counters + 1, s);
     } else {
-        e = launch_rollout(a, cfg, s, &tail);
+        e = cfg.pipe ? launch_rollout_pipe(a, cfg, s, &tail) : launch_rollout(a, cfg, s, &tail);
         if (e == hipSuccess) e = mark(1);
         if (e == hipSuccess)
             e = launch_update_sum(ctx->S, ctx->du, a.K, a.N, ctx->ld, lambda, u_in, ctx->u_upd, dg, ap,
-                                  ctx->counters + 1, ctx->cu_count, s);
+                                  ctx->counters + 1, 4 * ctx->cu_count, s);
     }
     return e;
 }
@@ -448,7 +448,13 @@ mppi_status mppi_rollout(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh, c
     RolloutArgs a = rollout_args(*veh, *cost, *solve);
     a.x_hat = x_hat; a.x_ref = x_ref; a.obs = obs; a.M = M; a.u_nom = u_nom;
     a.du = du; a.ld = ld; a.S = S; a.states = states;
-    HIP_TRY(ctx, launch_rollout(a, config_for(ctx, solve->K, solve->N, M), (hipStream_t)stream));
+    const LaunchConfig cfg = config_for(ctx, solve->K, solve->N, M);
+    if (cfg.pipe && !states && M <= kPipeMaxM)
+        HIP_TRY(ctx, launch_rollout_pipe(a, LaunchConfig{cfg.block, cfg.lanes, cfg.unroll, 0, 1},
+                                         (hipStream_t)stream));
+    else
+        HIP_TRY(ctx, launch_rollout(a, LaunchConfig{cfg.block, cfg.lanes, cfg.unroll, 0, 0},
+                                    (hipStream_t)stream));
     return MPPI_OK;
 }
 
@@ -458,6 +464,7 @@ mppi_status mppi_get_config(const mppi_ctx* ctx, int32_t K, int32_t N, int32_t M
     if (!ctx || !out || K < 1 || N < 1 || M < 0) return MPPI_E_INVALID_ARG;
     const LaunchConfig c = config_for(ctx, K, N, M);
     out->block = c.block; out->lanes = c.lanes; out->unroll = c.unroll; out->fused = c.fused;
+    out->pipe = c.pipe;
     return MPPI_OK;
 }
 
@@ -465,8 +472,9 @@ mppi_status mppi_set_config(mppi_ctx* ctx, int32_t K, int32_t N, int32_t M,
                             const mppi_launch_config* cfg)
 {
     if (!ctx || !cfg || K < 1 || N < 1 || M < 0) return MPPI_E_INVALID_ARG;
-    const LaunchConfig c{cfg->block, cfg->lanes, cfg->unroll, cfg->fused};
-    if (!valid_config(c)) return fail(ctx, MPPI_E_INVALID_ARG, "set_config: invalid shape");
+    const LaunchConfig c{cfg->block, cfg->lanes, cfg->unroll, cfg->fused, cfg->pipe};
+    if (!valid_config(c) || (c.pipe && M > kPipeMaxM))
+        return fail(ctx, MPPI_E_INVALID_ARG, "set_config: invalid shape");
     ctx->tuned[size_class(K, N, M)] = c;
     return MPPI_OK;
 }
@@ -497,13 +505,16 @@ mppi_status mppi_autotune(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh, 
                            [](int) { return hipSuccess; });
     };
     std::vector<LaunchConfig> cands;
-    for (int fused : {0, 1})
+    for (int variant : {0, 1, 2, 3})   // one-wave stored / single pass, wave-specialised ditto
         for (int lanes : {1, 2, 4, 8}) {
+            const bool pipe = variant >= 2, fused = variant & 1;
             if (lanes > 1 && M < 2 * lanes) continue;        // nothing to divide
+            if (pipe && M > kPipeMaxM) continue;
             for (int block : {64, 128, 256})
                 for (int unroll : {1, 4}) {
                     if (unroll > 1 && M < 8) continue;
-                    cands.push_back(LaunchConfig{block, lanes, unroll, fused});
+                    if (pipe && block != 64) continue;   // its workgroup is 64 (2 + lanes)
+                    cands.push_back(LaunchConfig{block, lanes, unroll, fused ? 1 : 0, pipe ? 1 : 0});
                 }
         }
     LaunchConfig best_c{};
@@ -526,7 +537,7 @@ mppi_status mppi_autotune(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh, 
     ctx->tuned[size_class(solve->K, solve->N, M)] = best_c;
     if (best) {
         best->block = best_c.block; best->lanes = best_c.lanes; best->unroll = best_c.unroll;
-        best->fused = best_c.fused;
+        best->fused = best_c.fused; best->pipe = best_c.pipe;
     }
     return MPPI_OK;
 }

@@ -36,6 +36,7 @@ struct LaunchConfig {
     int lanes;      // 1, 2, 4, 8
     int unroll;     // 1, 4
     int fused = 0;  // 1: single pass (per-wave partial sums), 0: stored delta_u
+    int pipe = 0;   // 1: wave-specialised rollouts (stored delta_u; block is 64 (2 + lanes))
 };
 
 bool valid_config(const LaunchConfig& c);
@@ -68,8 +69,13 @@ struct ApplyArgs {
 // Rollouts (with tail: and the full update's weight statistics).
 hipError_t launch_rollout(const RolloutArgs& a, const LaunchConfig& cfg, hipStream_t stream,
                           const UpdateTail* tail = nullptr);
+// Wave-specialised rollouts (stored delta_u) for M <= kPipeMaxM (the LDS of a
+// workgroup holds the obstacles and the hand-over buffers).
+constexpr int kPipeMaxM = 384;
+hipError_t launch_rollout_pipe(const RolloutArgs& a, const LaunchConfig& cfg, hipStream_t stream,
+                               const UpdateTail* tail = nullptr);
 // Waves of a rollout launch of this shape (one statistics record each).
-int rollout_waves(int K, const LaunchConfig& c);
+int rollout_waves(int K, const LaunchConfig& c);   // not for pipe shapes
 hipError_t launch_rollout_fused(const RolloutArgs& a, const LaunchConfig& c, const UpdateTail& tail,
                                 hipStream_t stream);
 // sum_grid_cap: most workgroups (the rows are shared out among them).

@@ -71,6 +71,78 @@ __global__ __launch_bounds__(256) void rollout_fused_kernel(
     }
 }
 
+// Wave-specialised rollouts: one workgroup of 2 + L waves per 64 samples -- noise,
+// rotation, and L translation-and-cost waves -- handing chunks of steps over through
+// LDS; with tail.stat the translation waves write the weight statistics (single pass,
+// kFused: and their partial sums, delta_u not stored) and the last workgroup reduces
+// them.
+template <int L, int U, bool kLag, bool kFused>
+__global__ __launch_bounds__(64 * (2 + 8)) void rollout_pipe_kernel(
+    RolloutParams a, const float* __restrict__ x_hat, const float* __restrict__ x_ref,
+    const mppi_obstacle* __restrict__ obs, const float* __restrict__ u_nom,
+    float* __restrict__ du_out, float* __restrict__ S_out, UpdateTail tail)
+{
+    extern __shared__ float4 lds[];       // obstacles, then PipeLds
+    float4* obs_lds = lds;
+    PipeLds& P = *reinterpret_cast<PipeLds*>(lds + kObsHeaderFloat4 + 2 * a.M);
+    const float phx = x_hat[0], phy = x_hat[1], phz = x_hat[2];
+    stage_obstacles(obs_lds, obs, a.M, phx, phy, phz, a.cp.margin);
+    __syncthreads();
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nch = (a.N + kPipeChunk - 1) / kPipeChunk;
+    int sb = lane, q = 0;
+    if (wv >= 2) {                        // 64 / L samples per translation wave
+        sb = (wv - 2) * (64 / L) + lane / L;
+        q = lane % L;
+    }
+    const int k = blockIdx.x * 64 + sb;
+    const bool valid = k < a.K;
+    const int kk = valid ? k : a.K - 1;
+    const bool writer = valid && q == 0;
+
+    State x;
+    x.px = 0.0f; x.py = 0.0f; x.pz = 0.0f;
+    x.qw = x_hat[3]; x.qx = x_hat[4]; x.qy = x_hat[5]; x.qz = x_hat[6];
+    x.vx = x_hat[7]; x.vy = x_hat[8]; x.vz = x_hat[9];
+    x.wx = x_hat[10]; x.wy = x_hat[11]; x.wz = x_hat[12];
+    x.T0 = x_hat[13]; x.T1 = x_hat[14]; x.T2 = x_hat[15]; x.T3 = x_hat[16];
+    float up[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    KahanSum S;
+    int tested = 0;
+    if (wv >= 2)                           // state j = 0 is scored too (Eq. (17))
+        S.add(tracking_cost(a.cp, x, x_ref[0] - phx, x_ref[1] - phy, x_ref[2] - phz, x_ref) +
+              obstacle_cost<L, U>(a.cp, x.px, x.py, x.pz, obs_lds, a.M, q, tested));
+
+    for (int ph = 0; ph < nch + 2; ++ph) {
+        if (wv == 0) {
+            if (ph < nch) pipe_noise_chunk<!kFused>(a, u_nom, du_out, writer, kk, ph, up, P, lane);
+        } else if (wv == 1) {
+            if (ph >= 1 && ph <= nch) pipe_rotation_chunk<kLag>(a, x, ph - 1, P, lane);
+        } else if (ph >= 2) {
+            pipe_translation_chunk<L, U>(a, x_ref, obs_lds, phx, phy, phz, x, S, tested, ph - 2, sb, q, P);
+        }
+        __syncthreads();
+    }
+    if (wv >= 2) {
+        if (writer) S_out[k] = S.s;
+        if (a.obs_tests) {
+            const unsigned long long samples = __popcll(__ballot(writer));
+            if (lane == 0) atomicAdd(a.obs_tests, samples * (unsigned long long)tested);
+        }
+        const int w = blockIdx.x * L + (wv - 2);
+        if (kFused)
+            fused_wave_partials<L>(a, tail.lambda, wave_sums(S.s, k, q, valid, tail.lambda), kk, q,
+                                   tail.stat + w, tail.part + (size_t)w * 4 * a.N, tail.rho_run);
+        else if (tail.stat)
+            write_wave_stat(tail.stat + w, wave_sums(S.s, k, q, valid, tail.lambda), false);
+    }
+    if (tail.stat && last_to_arrive(tail.counter)) {
+        reduce_wave_stats(tail.stat, (int)gridDim.x * L, tail.lambda, L, tail.diag,
+                          kFused ? tail.list_idx : nullptr, tail.list_s, tail.list_n);
+        if (kFused && threadIdx.x == 0) *tail.rho_run = 0x7f800000u;   // every wave has published
+    }
+}
+
 // Weighted sum of the stored delta_u, rows 4 j + d taken in turn by at most one
 // workgroup per CU (fewer arrivals to fence); the last workgroup applies and advances
 // (Eqs. (5), (12)-(15), Sec. IV-B).
@@ -162,7 +234,8 @@ bool valid_config(const LaunchConfig& c)
 {
     return (c.block == 64 || c.block == 128 || c.block == 256) &&
            (c.lanes == 1 || c.lanes == 2 || c.lanes == 4 || c.lanes == 8) &&
-           (c.unroll == 1 || c.unroll == 4) && (c.fused == 0 || c.fused == 1);
+           (c.unroll == 1 || c.unroll == 4) && (c.fused == 0 || c.fused == 1) &&
+           (c.pipe == 0 || c.pipe == 1);
 }
 
 int rollout_waves(int K, const LaunchConfig& c)
@@ -225,6 +298,44 @@ hipError_t launch_rollout_fused(const RolloutArgs& a, const LaunchConfig& c, con
 {
     if (!tail.stat || !tail.part || !tail.rho_run || !tail.list_idx) return hipErrorInvalidValue;
     return launch_rollout_any(a, c, tail, true, stream);
+}
+
+template <int L, int U>
+static hipError_t launch_pipe_lu(const RolloutArgs& a, const UpdateTail& tail, bool fused,
+                                 hipStream_t stream)
+{
+    const int grid = (a.K + 63) / 64;
+    const RolloutParams p{a.mp, a.cp, a.np, a.M, a.K, a.N, a.ld, a.obs_tests};
+    auto kernel = fused ? (a.mp.lag ? rollout_pipe_kernel<L, U, true, true> : rollout_pipe_kernel<L, U, false, true>)
+                        : (a.mp.lag ? rollout_pipe_kernel<L, U, true, false> : rollout_pipe_kernel<L, U, false, false>);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(64 * (2 + L)), pipe_lds_bytes(a.M), stream, p, a.x_hat,
+                       a.x_ref, a.obs, a.u_nom, a.du, a.S, tail);
+    return hipGetLastError();
+}
+
+template <int L>
+static hipError_t launch_pipe_l(const RolloutArgs& a, const LaunchConfig& c, const UpdateTail& tail,
+                                hipStream_t stream)
+{
+    const bool fused = c.fused != 0;
+    return c.unroll == 4 ? launch_pipe_lu<L, 4>(a, tail, fused, stream)
+                         : launch_pipe_lu<L, 1>(a, tail, fused, stream);
+}
+
+hipError_t launch_rollout_pipe(const RolloutArgs& a, const LaunchConfig& c, hipStream_t stream,
+                               const UpdateTail* tail)
+{
+    if (!valid_config(c) || !c.pipe || a.M > kPipeMaxM) return hipErrorInvalidValue;
+    if (c.fused && (!tail || !tail->stat || !tail->part || !tail->rho_run || !tail->list_idx))
+        return hipErrorInvalidValue;
+    UpdateTail none{};
+    const UpdateTail& t = tail ? *tail : none;
+    switch (c.lanes) {
+    case 1: return launch_pipe_l<1>(a, c, t, stream);
+    case 2: return launch_pipe_l<2>(a, c, t, stream);
+    case 4: return launch_pipe_l<4>(a, c, t, stream);
+    default: return launch_pipe_l<8>(a, c, t, stream);
+    }
 }
 
 hipError_t launch_update_sum(const float* S, const float* du, int K, int N, int ld, float lambda,

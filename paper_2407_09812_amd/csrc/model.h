@@ -114,6 +114,16 @@ __device__ __forceinline__ float unit_uniform(uint32_t w)
     return __uint_as_float((w >> 9) | 0x3F800000u) - 0.99999994f;
 }
 
+// v as computed, in a register of its own: the empty asm statement hides how v was
+// produced, so the compiler cannot fuse its producing multiply into a consumer.  Values
+// that the kernels hand over between waves or lanes pass through it everywhere, so
+// that every launch shape computes them -- and what follows -- the same way.
+__device__ __forceinline__ float opaque(float v)
+{
+    asm("" : "+v"(v));
+    return v;
+}
+
 // delta_u for sample k, step j: Philox counter (k, j, t, seed_hi), Box-Muller on
 // (u0, u1) and (u2, u3).  v_sin/v_cos take revolutions, so sin(2 pi u) is one op.
 __device__ __forceinline__ void draw_noise(const NoiseParams& np, uint32_t k, uint32_t j,
@@ -125,10 +135,10 @@ __device__ __forceinline__ void draw_noise(const NoiseParams& np, uint32_t k, ui
     const float neg2ln2 = -1.38629436112f;   // -2 ln 2: ln u = ln 2 * log2 u
     const float r0 = __builtin_amdgcn_sqrtf(neg2ln2 * __builtin_amdgcn_logf(u0));
     const float r1 = __builtin_amdgcn_sqrtf(neg2ln2 * __builtin_amdgcn_logf(u2));
-    du[0] = np.sigma[0] * (r0 * __builtin_amdgcn_cosf(u1));
-    du[1] = np.sigma[1] * (r0 * __builtin_amdgcn_sinf(u1));
-    du[2] = np.sigma[2] * (r1 * __builtin_amdgcn_cosf(u3));
-    du[3] = np.sigma[3] * (r1 * __builtin_amdgcn_sinf(u3));
+    du[0] = opaque(np.sigma[0] * (r0 * __builtin_amdgcn_cosf(u1)));
+    du[1] = opaque(np.sigma[1] * (r0 * __builtin_amdgcn_sinf(u1)));
+    du[2] = opaque(np.sigma[2] * (r1 * __builtin_amdgcn_cosf(u3)));
+    du[3] = opaque(np.sigma[3] * (r1 * __builtin_amdgcn_sinf(u3)));
 }
 
 // ---------------------------------------------------------------------------
@@ -181,7 +191,7 @@ struct Body {
     float wx, wy, wz;
 };
 
-#define MPPI_BODY_FIELDS(X) X(qw) X(qx) X(qy) X(qz) X(vx) X(vy) X(vz) X(wx) X(wy) X(wz)
+#define MPPI_ROT_FIELDS(X) X(qw) X(qx) X(qy) X(qz) X(wx) X(wy) X(wz)
 
 __device__ __forceinline__ void body_derivative(const ModelParams& P, const Body& b, const Wrench& W,
                                                 Body& d)
@@ -203,14 +213,23 @@ __device__ __forceinline__ void body_derivative(const ModelParams& P, const Body
     d.wz = (W.tz - P.G[2] * (b.wx * b.wy)) * P.J_inv[2];
 }
 
+// Accelerations v' at the four RK4 stage points of one step.
+struct StageAccel {
+    float x[4], y[4], z[4];
+};
+
 // One step x <- x + f_RK4(x, Tc, dt) with the command held, then q <- q / |q|.
 // This is classic RK4 on the 17-value state, arranged to skip work that is known in
 // closed form: the wrench at each stage point comes from the stage thrusts of the
 // linear lag (W(T) + c_s W(T_cmd - T), exact since the allocation is linear), and
 // since nothing depends on the position its update is p + h v + h^2/6 (a1 + a2 + a3),
-// which is what RK4's four stage velocities sum to.
+// which is what RK4's four stage velocities sum to.  Nothing in the rotational part
+// (q, omega, T) depends on p or v, so the step splits into rk4_rotational, which also
+// returns the stage accelerations, and rk4_translational, which integrates p and v
+// from them.
 template <bool kLag>
-__device__ __forceinline__ void rk4_step(const ModelParams& P, State& x, const float Tc[4])
+__device__ __forceinline__ void rk4_rotational(const ModelParams& P, State& x, const float Tc[4],
+                                               StageAccel& A)
 {
     const float h = P.dt, h2 = 0.5f * P.dt, h6 = P.dt * (1.0f / 6.0f);
     Wrench W1, W2, W3, W4;
@@ -232,27 +251,24 @@ __device__ __forceinline__ void rk4_step(const ModelParams& P, State& x, const f
     const Body b{x.qw, x.qx, x.qy, x.qz, x.vx, x.vy, x.vz, x.wx, x.wy, x.wz};
     Body k, bs, acc;
     body_derivative(P, b, W1, k);                                // k1
-    float ax = k.vx, ay = k.vy, az = k.vz;
+    A.x[0] = opaque(k.vx); A.y[0] = opaque(k.vy); A.z[0] = opaque(k.vz);
 #define STAGE1(f) acc.f = k.f; bs.f = fmaf(h2, k.f, b.f);
-    MPPI_BODY_FIELDS(STAGE1)
+    MPPI_ROT_FIELDS(STAGE1)
 #undef STAGE1
     body_derivative(P, bs, W2, k);                               // k2
-    ax += k.vx; ay += k.vy; az += k.vz;
+    A.x[1] = opaque(k.vx); A.y[1] = opaque(k.vy); A.z[1] = opaque(k.vz);
 #define STAGE2(f) acc.f = fmaf(2.0f, k.f, acc.f); bs.f = fmaf(h2, k.f, b.f);
-    MPPI_BODY_FIELDS(STAGE2)
+    MPPI_ROT_FIELDS(STAGE2)
 #undef STAGE2
     body_derivative(P, bs, W3, k);                               // k3
-    ax += k.vx; ay += k.vy; az += k.vz;
+    A.x[2] = opaque(k.vx); A.y[2] = opaque(k.vy); A.z[2] = opaque(k.vz);
 #define STAGE3(f) acc.f = fmaf(2.0f, k.f, acc.f); bs.f = fmaf(h, k.f, b.f);
-    MPPI_BODY_FIELDS(STAGE3)
+    MPPI_ROT_FIELDS(STAGE3)
 #undef STAGE3
     body_derivative(P, bs, W4, k);                               // k4
-    const float hh6 = h * h6;
-    x.px = fmaf(hh6, ax, fmaf(h, b.vx, x.px));
-    x.py = fmaf(hh6, ay, fmaf(h, b.vy, x.py));
-    x.pz = fmaf(hh6, az, fmaf(h, b.vz, x.pz));
+    A.x[3] = opaque(k.vx); A.y[3] = opaque(k.vy); A.z[3] = opaque(k.vz);
 #define STAGE4(f) x.f = fmaf(h6, acc.f + k.f, b.f);
-    MPPI_BODY_FIELDS(STAGE4)
+    MPPI_ROT_FIELDS(STAGE4)
 #undef STAGE4
     const float n2 = x.qw * x.qw + x.qx * x.qx + x.qy * x.qy + x.qz * x.qz;
     const float inv = __builtin_amdgcn_rsqf(n2);
@@ -263,6 +279,29 @@ __device__ __forceinline__ void rk4_step(const ModelParams& P, State& x, const f
     } else {
         x.T0 = Tc[0]; x.T1 = Tc[1]; x.T2 = Tc[2]; x.T3 = Tc[3];
     }
+}
+
+// p and v over the step from the stage accelerations of rk4_rotational.
+__device__ __forceinline__ void rk4_translational(const ModelParams& P, State& x, const StageAccel& A)
+{
+    const float h = P.dt, h6 = P.dt * (1.0f / 6.0f), hh6 = h * h6;
+    const float ax = (A.x[0] + A.x[1]) + A.x[2];
+    const float ay = (A.y[0] + A.y[1]) + A.y[2];
+    const float az = (A.z[0] + A.z[1]) + A.z[2];
+    x.px = fmaf(hh6, ax, fmaf(h, x.vx, x.px));
+    x.py = fmaf(hh6, ay, fmaf(h, x.vy, x.py));
+    x.pz = fmaf(hh6, az, fmaf(h, x.vz, x.pz));
+    x.vx = fmaf(h6, fmaf(2.0f, A.x[2], fmaf(2.0f, A.x[1], A.x[0])) + A.x[3], x.vx);
+    x.vy = fmaf(h6, fmaf(2.0f, A.y[2], fmaf(2.0f, A.y[1], A.y[0])) + A.y[3], x.vy);
+    x.vz = fmaf(h6, fmaf(2.0f, A.z[2], fmaf(2.0f, A.z[1], A.z[0])) + A.z[3], x.vz);
+}
+
+template <bool kLag>
+__device__ __forceinline__ void rk4_step(const ModelParams& P, State& x, const float Tc[4])
+{
+    StageAccel A;
+    rk4_rotational<kLag>(P, x, Tc, A);
+    rk4_translational(P, x, A);
 }
 
 // ---------------------------------------------------------------------------
@@ -286,9 +325,10 @@ __device__ __forceinline__ float tracking_cost(const CostParams& C, const State&
     return c;
 }
 
-// Sum / OR over the L consecutive lanes that share one sample.  xor partners 1 and 2
-// use DPP quad permutations; 4 uses a cross-lane shuffle.  Every lane of the group
-// ends with the same value (the additions pair the same operands in every lane).
+// Sum / OR over the L consecutive lanes that share one sample: DPP quad permutations
+// (xor 1, xor 2), then for eight lanes the half-row mirror, which pairs each lane of
+// one quad with a lane of the other (both quads already hold their sums).  Every lane
+// of the group ends with the same value (the additions pair the same operands).
 __device__ __forceinline__ float dpp_xor1(float v)
 {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
@@ -303,7 +343,8 @@ __device__ __forceinline__ float group_sum(float v)
 {
     if (L >= 2) v += dpp_xor1(v);
     if (L >= 4) v += dpp_xor2(v);
-    if (L >= 8) v += __shfl_xor(v, 4);
+    if (L >= 8)
+        v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false));
     return v;
 }
 
@@ -315,7 +356,9 @@ __device__ __forceinline__ float dpp_extreme_step(float x)
 {
     const float y = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x),
                                                                kCtrl, kRowMask, 0xF, false));
-    return kMax ? fmaxf(x, y) : fminf(x, y);
+    // a select, not fmaxf/fminf: no NaN canonicalisation; the caller clamps the bin
+    // indices with fmaxf/fminf, which keeps them in range for any input
+    return kMax ? (y > x ? y : x) : (y < x ? y : x);
 }
 
 template <bool kMax>

@@ -179,6 +179,117 @@ __device__ __forceinline__ float rollout_sample(const RolloutParams& a, const fl
 }
 
 // ---------------------------------------------------------------------------
+// Wave-specialised rollouts: one workgroup per 64 samples, 2 + L waves.  Nothing in
+// the rotational part of a step (q, omega, rotor thrusts) depends on p or v, so the
+// step's work is split across waves that run on different SIMDs: wave 0 draws the
+// noise and forms u and the input costs, wave 1 runs the controller and the rotational
+// RK4 and hands over the stage accelerations and the new attitude and rates, and waves
+// 2 .. 2 + L - 1 integrate p and v and score the state (L lanes per sample dividing
+// the obstacle tests, as in rollout_sample).  The roles hand over chunks of kPipeChunk
+// steps through double-buffered LDS, one workgroup barrier per chunk, each role one
+// chunk behind the previous.  The arithmetic is rollout_sample's, operation for
+// operation, so the results are the same.
+// ---------------------------------------------------------------------------
+
+constexpr int kPipeChunk = 4;
+
+struct PipeLds {
+    float4 u[2][kPipeChunk][64];         // u_j per sample
+    float cu[2][kPipeChunk][64];         // input and input-change cost of step j
+    float4 r[2][kPipeChunk][5][64];      // a.x, a.y, a.z (4 stages each), q, (omega, cost)
+};
+
+__host__ __device__ constexpr size_t pipe_lds_bytes(int M)
+{
+    return obstacle_lds_bytes(M) + sizeof(PipeLds);
+}
+
+// Noise role: chunk c of sample k (kk: k clamped to K - 1).
+template <bool kStoreDu>
+__device__ __forceinline__ void pipe_noise_chunk(const RolloutParams& a, const float* __restrict__ u_nom,
+                                                 float* __restrict__ du_out, bool writer, int kk,
+                                                 int c, float (&up)[4], PipeLds& P, int lane)
+{
+    const size_t ld = (size_t)a.ld;
+    for (int s = 0; s < kPipeChunk; ++s) {
+        const int j = c * kPipeChunk + s;
+        if (j >= a.N) break;                                   // uniform
+        float du[4], u[4];
+        draw_noise(a.np, (uint32_t)kk, (uint32_t)j, du);
+        if (kStoreDu && writer) {
+            float* dst = du_out + (size_t)(4 * j) * ld + kk;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) dst[(size_t)d * ld] = du[d];
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) u[d] = u_nom[4 * j + d] + du[d];
+        float cu = 0.0f;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) cu = fmaf(a.cp.R[d] * u[d], u[d], cu);
+        if (j > 0) {
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const float e = u[d] - up[d];
+                cu = fmaf(a.cp.Rd[d] * e, e, cu);
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) up[d] = u[d];
+        P.u[c & 1][s][lane] = make_float4(u[0], u[1], u[2], u[3]);
+        P.cu[c & 1][s][lane] = cu;
+    }
+}
+
+// Rotation role: chunk c (x holds q, omega and the rotor thrusts).
+template <bool kLag>
+__device__ __forceinline__ void pipe_rotation_chunk(const RolloutParams& a, State& x, int c, PipeLds& P,
+                                                    int lane)
+{
+    for (int s = 0; s < kPipeChunk; ++s) {
+        const int j = c * kPipeChunk + s;
+        if (j >= a.N) break;
+        const float4 uv = P.u[c & 1][s][lane];
+        const float u[4] = {uv.x, uv.y, uv.z, uv.w};
+        float Tc[4];
+        rate_controller(a.mp, x.wx, x.wy, x.wz, u, Tc);
+        StageAccel A;
+        rk4_rotational<kLag>(a.mp, x, Tc, A);
+        P.r[c & 1][s][0][lane] = make_float4(A.x[0], A.x[1], A.x[2], A.x[3]);
+        P.r[c & 1][s][1][lane] = make_float4(A.y[0], A.y[1], A.y[2], A.y[3]);
+        P.r[c & 1][s][2][lane] = make_float4(A.z[0], A.z[1], A.z[2], A.z[3]);
+        P.r[c & 1][s][3][lane] = make_float4(x.qw, x.qx, x.qy, x.qz);
+        P.r[c & 1][s][4][lane] = make_float4(x.wx, x.wy, x.wz, P.cu[c & 1][s][lane]);
+    }
+}
+
+// Translation and cost role: chunk c for the sample at position sb of the workgroup,
+// lane q of its L lanes (x holds p relative to p_hat, and v).
+template <int L, int U>
+__device__ __forceinline__ void pipe_translation_chunk(const RolloutParams& a,
+                                                       const float* __restrict__ x_ref,
+                                                       const float4* __restrict__ obs_lds,
+                                                       float phx, float phy, float phz, State& x,
+                                                       KahanSum& S, int& tested, int c, int sb,
+                                                       int q, const PipeLds& P)
+{
+    for (int s = 0; s < kPipeChunk; ++s) {
+        const int j = c * kPipeChunk + s;
+        if (j >= a.N) break;
+        const float4 ax = P.r[c & 1][s][0][sb], ay = P.r[c & 1][s][1][sb];
+        const float4 az = P.r[c & 1][s][2][sb], qv = P.r[c & 1][s][3][sb];
+        const float4 wv = P.r[c & 1][s][4][sb];
+        const StageAccel A{{ax.x, ax.y, ax.z, ax.w}, {ay.x, ay.y, ay.z, ay.w}, {az.x, az.y, az.z, az.w}};
+        rk4_translational(a.mp, x, A);
+        x.qw = qv.x; x.qx = qv.y; x.qy = qv.z; x.qz = qv.w;
+        x.wx = wv.x; x.wy = wv.y; x.wz = wv.z;
+        const float* ref = x_ref + (size_t)13 * (j + 1);
+        const float cx = tracking_cost(a.cp, x, ref[0] - phx, ref[1] - phy, ref[2] - phz, ref) +
+                         obstacle_cost<L, U>(a.cp, x.px, x.py, x.pz, obs_lds, a.M, q, tested);
+        S.add(wv.w + cx);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Block reductions (wave64 shuffles, then LDS across waves)
 // ---------------------------------------------------------------------------
 
@@ -631,12 +742,22 @@ __device__ __forceinline__ void update_sum_row(const float* __restrict__ S, cons
         const int K4 = K >> 2;
         const float4* s4 = reinterpret_cast<const float4*>(src);
         const float4* c4 = reinterpret_cast<const float4*>(S);
-        for (int i = tid; i < K4; i += blockDim.x) {
-            const float4 a = s4[i], c = c4[i];
-            acc = fmaf(a.x, wt(c.x), acc);
-            acc = fmaf(a.y, wt(c.y), acc);
-            acc = fmaf(a.z, wt(c.z), acc);
-            acc = fmaf(a.w, wt(c.w), acc);
+        const int stride = blockDim.x;
+        for (int i = tid; i < K4; i += 4 * stride) {     // four float4 pairs in flight
+            float4 a[4], c[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int idx = i + u * stride;
+                a[u] = idx < K4 ? s4[idx] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                c[u] = idx < K4 ? c4[idx] : make_float4(INFINITY, INFINITY, INFINITY, INFINITY);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                acc = fmaf(a[u].x, wt(c[u].x), acc);
+                acc = fmaf(a[u].y, wt(c[u].y), acc);
+                acc = fmaf(a[u].z, wt(c[u].z), acc);
+                acc = fmaf(a[u].w, wt(c[u].w), acc);
+            }
         }
         for (int k = 4 * K4 + tid; k < K; k += blockDim.x) acc = fmaf(src[k], wt(S[k]), acc);
     } else {

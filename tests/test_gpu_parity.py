@@ -165,7 +165,7 @@ def test_rollout_parity_every_launch_shape(lib, ctx, orc, lanes, block, unroll):
     P = DeviceProblem(lib, W.c2_line(K=700, N=60))
     lib.mppi_set_config(ctx, P.K, P.N, P.M, block, lanes, unroll)
     assert lib.mppi_get_config(ctx, P.K, P.N, P.M) == dict(block=block, lanes=lanes, unroll=unroll,
-                                                            fused=0)
+                                                            fused=0, pipe=0)
     du, S, st = run_rollout(lib, ctx, P)
     check_rollouts(orc, P, du, S, st, np.arange(P.K))
     P3 = DeviceProblem(lib, W.c3_agile(K=2000, N=120))

@@ -1,0 +1,122 @@
+"""Wave-specialised rollouts (launch shape pipe = 1): noise, rotational dynamics and
+translation-with-costs on different waves of a workgroup, handing chunks of steps
+over through LDS.  The arithmetic is the one-wave kernel's operation for operation;
+the compiler's fusion of multiplies into adds still differs between the two kernels
+at a few places, so costs agree to the last unit or two of binary32.  Bars, for every
+lane count and unroll, ragged K and N not a multiple of the chunk: the perturbations
+bit for bit; the costs within 1e-5 relative (a state on an obstacle surface may flip
+the collision indicator: then a whole multiple of the collision constant); the whole
+update within 1e-4 (sigma floors); the obstacle-test count exactly; and the oracle at
+1e-4 on one shape.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from gpu_support import TOL, DeviceProblem, check_costs, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2407_09812_amd as lib
+    return lib
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    c = lib.Context(0)
+    lib.mppi_reserve(c, 16384, 200, 256)
+    yield c
+    c.close()
+
+
+def rollout(lib, ctx, P, lanes, unroll, pipe):
+    lib.mppi_set_config(ctx, P.K, P.N, P.M, 64, lanes, unroll, 0, pipe)
+    du = torch.full((P.N * 4 * P.K,), float("nan"), device="cuda")
+    S = torch.full((P.K,), float("nan"), device="cuda")
+    lib.mppi_rollout(ctx, P.sc.veh, P.sc.cost, P.solve, P.x_hat, P.x_ref, P.obs, P.M, P.u_nom, du,
+                     P.K, S)
+    torch.cuda.synchronize()
+    return du, S
+
+
+def update(lib, ctx, P, lanes, unroll, pipe, fused=0):
+    lib.mppi_set_config(ctx, P.K, P.N, P.M, 64, lanes, unroll, fused, pipe)
+    un, ua, dg = P.u_nom.clone(), torch.empty(8, device="cuda"), lib.new_diag()
+    lib.mppi_profile_enable(ctx, True)
+    lib.mppi_profile_read(ctx)
+    lib.mppi_update(ctx, P.sc.veh, P.sc.cost, P.solve, P.x_hat, P.x_ref, P.obs, P.M, un, ua, dg)
+    prof = lib.mppi_profile_read(ctx)
+    lib.mppi_profile_enable(ctx, False)
+    torch.cuda.synchronize()
+    return un, ua, dg, prof["obstacle_tests"]
+
+
+SCENES = [("c2", lambda: W.c2_line(K=700, N=61)), ("c3", lambda: W.c3_agile(K=2000, N=122)),
+          ("c1", lambda: W.c1_plain(K=130, N=7)), ("paper", W.paper_preset)]
+
+
+@pytest.mark.parametrize("scene", [s[0] for s in SCENES])
+def test_pipe_equals_one_wave_kernel_bitwise(lib, ctx, scene):
+    sc = dict(SCENES)[scene]()
+    P = DeviceProblem(lib, sc, t=2)
+    for lanes in (1, 2, 4, 8):
+        if lanes > 1 and P.M < 2 * lanes:
+            continue
+        for unroll in (1, 4):
+            du0, S0 = rollout(lib, ctx, P, lanes, unroll, 0)
+            du1, S1 = rollout(lib, ctx, P, lanes, unroll, 1)
+            assert torch.equal(du0, du1), (scene, lanes, unroll)
+            s0, s1 = S0.double().cpu().numpy(), S1.double().cpu().numpy()
+            r = (s1 - s0) / sc.cost["obs_collision"]
+            flip = np.abs(r) >= 0.5
+            assert np.abs(r[flip] - np.round(r[flip])).max(initial=0.0) * sc.cost["obs_collision"] \
+                <= 1e-5 * np.abs(s0[flip]).max(initial=1.0)
+            e_S = (np.abs(s1 - s0) / np.maximum(np.abs(s0), 1.0))[~flip].max()
+            n_diff = int((s1 != s0).sum())
+            a = update(lib, ctx, P, lanes, unroll, 0)
+            b = update(lib, ctx, P, lanes, unroll, 1)
+            sigma = np.asarray(sc.sigma)
+            e_u = rel_err(b[0].view(-1, 4).double().cpu().numpy(), a[0].view(-1, 4).double().cpu().numpy(),
+                          sigma).max()
+            e_a = rel_err(b[1].double().cpu().numpy(), a[1].double().cpu().numpy(), 1.0).max()
+            print(f"{scene} lanes={lanes} unroll={unroll}: costs differing {n_diff}/{P.K} (max rel "
+                  f"{e_S:.1e}, flips {int(flip.sum())}), update {e_u:.1e}, applied {e_a:.1e}, "
+                  f"obstacle tests {a[3]} / {b[3]}")
+            assert e_S <= 1e-5 and flip.sum() <= 2 and e_u <= TOL and e_a <= TOL
+            assert a[3] == b[3]
+            # single pass, both kernels
+            f0 = update(lib, ctx, P, lanes, unroll, 0, 1)
+            f1 = update(lib, ctx, P, lanes, unroll, 1, 1)
+            e_f = rel_err(f1[0].view(-1, 4).double().cpu().numpy(),
+                          f0[0].view(-1, 4).double().cpu().numpy(), sigma).max()
+            e_s = rel_err(f1[0].view(-1, 4).double().cpu().numpy(),
+                          a[0].view(-1, 4).double().cpu().numpy(), sigma).max()
+            print(f"   single pass: pipe vs one-wave {e_f:.1e}, vs stored {e_s:.1e}")
+            assert e_f <= TOL and e_s <= TOL and f1[3] == a[3]
+
+
+def test_pipe_rollouts_match_oracle(lib, ctx, orc):
+    sc = W.c3_agile(K=512, N=41)
+    P = DeviceProblem(lib, sc)
+    du, S = rollout(lib, ctx, P, 4, 4, 1)
+    ks = np.arange(0, P.K, 7)
+    _, du_o, S_o = orc.rollouts_subset(P.o_veh, P.o_cost, P.o_solve, ks, P.o_x_hat, P.o_u_nom,
+                                       P.o_x_ref, P.o_obs, want_states=False)
+    kt = torch.as_tensor(ks, device="cuda")
+    du_g = du.view(P.N, 4, P.K)[:, :, kt].permute(2, 0, 1).double().cpu().numpy()
+    S_g = S[kt].double().cpu().numpy()
+    e_du = rel_err(du_g, du_o, np.asarray(sc.sigma)).max()
+    e_S = rel_err(S_g, S_o, 1.0)
+    flips = np.abs(np.round((S_g - S_o) / sc.cost["obs_collision"])) >= 1
+    print(f"pipe vs oracle: du {e_du:.2e} S {e_S[~flips].max():.2e} collision-boundary {flips.sum()}")
+    assert e_du <= TOL and e_S[~flips].max() <= TOL and flips.sum() <= 2
+
+
+def test_pipe_rejects_too_many_obstacles(lib, ctx):
+    with pytest.raises(lib.MPPIError) as e:
+        lib.mppi_set_config(ctx, 1024, 50, 500, 64, 4, 1, 0, 1)
+    assert e.value.status == -1
