@@ -266,7 +266,7 @@ hipError_t update_core(mppi_ctx* ctx, const RolloutArgs& a, const LaunchConfig& 
         if (e == hipSuccess) e = mark(1);
         if (e == hipSuccess)
             e = launch_update_sum(ctx->S, ctx->du, a.K, a.N, ctx->ld, lambda, u_in, ctx->u_upd, dg, ap,
-                                  ctx->counters + 1, 4 * ctx->cu_count, s);
+                                  s);
     }
     return e;
 }

@@ -78,11 +78,10 @@ hipError_t launch_rollout_pipe(const RolloutArgs& a, const LaunchConfig& cfg, hi
 int rollout_waves(int K, const LaunchConfig& c);   // not for pipe shapes
 hipError_t launch_rollout_fused(const RolloutArgs& a, const LaunchConfig& c, const UpdateTail& tail,
                                 hipStream_t stream);
-// sum_grid_cap: most workgroups (the rows are shared out among them).
+// The stored form's weighted sum, then the apply and advance (two launches).
 hipError_t launch_update_sum(const float* S, const float* du, int K, int N, int ld, float lambda,
                              const float* u_in, float* u_upd, const mppi_diag* diag,
-                             const ApplyArgs& ap, unsigned int* counter, int sum_grid_cap,
-                             hipStream_t stream);
+                             const ApplyArgs& ap, hipStream_t stream);
 hipError_t launch_merge_sum(const float* part, int N, const int* list_idx, const float* list_s,
                             const int* list_n, const float* u_in, float* u_upd,
                             const mppi_diag* diag, const ApplyArgs& ap, unsigned int* counter,

@@ -143,21 +143,14 @@ __global__ __launch_bounds__(64 * (2 + 8)) void rollout_pipe_kernel(
     }
 }
 
-// Weighted sum of the stored delta_u, rows 4 j + d taken in turn by at most one
-// workgroup per CU (fewer arrivals to fence); the last workgroup applies and advances
-// (Eqs. (5), (12)-(15), Sec. IV-B).
+// Weighted sum of the stored delta_u, one workgroup per row 4 j + d (Eq. (5)).  The
+// apply and advance follow as their own launch: with hundreds of rows, a device-scope
+// fence in every workgroup (for a last-arrival tail) costs more than the launch.
 __global__ __launch_bounds__(kSumThreads) void update_sum_kernel(
     const float* __restrict__ S, const float* __restrict__ du, int K, int ld, float lambda,
-    const float* __restrict__ u_in, float* __restrict__ u_upd, const mppi_diag* __restrict__ diag,
-    ApplyArgs ap, unsigned int* __restrict__ counter)
+    const float* __restrict__ u_in, float* __restrict__ u_upd, const mppi_diag* __restrict__ diag)
 {
-    for (int row = blockIdx.x; row < 4 * ap.N; row += gridDim.x) {
-        update_sum_row(S, du, K, ld, lambda, u_in, u_upd, diag, row);
-        __syncthreads();                     // the row's LDS partials are reused
-    }
-    if (last_to_arrive(counter))
-        apply_shift_block(ap.P, ap.x_hat, u_upd, ap.u_nom, ap.u_apply, ap.N, ap.u_init, ap.alpha,
-                          diag);
+    update_sum_row(S, du, K, ld, lambda, u_in, u_upd, diag, blockIdx.x);
 }
 
 // Single pass: the listed waves' partial sums, 64 columns per workgroup; the last
@@ -340,12 +333,12 @@ hipError_t launch_rollout_pipe(const RolloutArgs& a, const LaunchConfig& c, hipS
 
 hipError_t launch_update_sum(const float* S, const float* du, int K, int N, int ld, float lambda,
                              const float* u_in, float* u_upd, const mppi_diag* diag,
-                             const ApplyArgs& ap, unsigned int* counter, int sum_grid_cap,
-                             hipStream_t stream)
+                             const ApplyArgs& ap, hipStream_t stream)
 {
-    const int grid = 4 * N < sum_grid_cap ? 4 * N : sum_grid_cap;
-    hipLaunchKernelGGL(update_sum_kernel, dim3(grid), dim3(kSumThreads), 0, stream, S, du, K, ld,
-                       lambda, u_in, u_upd, diag, ap, counter);
+    hipLaunchKernelGGL(update_sum_kernel, dim3(4 * N), dim3(kSumThreads), 0, stream, S, du, K, ld,
+                       lambda, u_in, u_upd, diag);
+    hipLaunchKernelGGL(apply_shift_kernel, dim3(1), dim3(256), 0, stream, ap.P, ap.x_hat, u_upd,
+                       ap.u_nom, ap.u_apply, ap.N, ap.u_init, ap.alpha, diag);
     return hipGetLastError();
 }
 
