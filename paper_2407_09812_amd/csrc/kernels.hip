@@ -84,7 +84,7 @@ __global__ __launch_bounds__(64 * (2 + 8)) void rollout_pipe_kernel(
 {
     extern __shared__ float4 lds[];       // obstacles, then PipeLds
     float4* obs_lds = lds;
-    PipeLds& P = *reinterpret_cast<PipeLds*>(lds + kObsHeaderFloat4 + 2 * a.M);
+    PipeLds& P = *reinterpret_cast<PipeLds*>(lds + obstacle_lds_float4(a.M));
     const float phx = x_hat[0], phy = x_hat[1], phz = x_hat[2];
     stage_obstacles(obs_lds, obs, a.M, phx, phy, phz, a.cp.margin);
     __syncthreads();
@@ -110,8 +110,7 @@ __global__ __launch_bounds__(64 * (2 + 8)) void rollout_pipe_kernel(
     KahanSum S;
     int tested = 0;
     if (wv >= 2)                           // state j = 0 is scored too (Eq. (17))
-        S.add(tracking_cost(a.cp, x, x_ref[0] - phx, x_ref[1] - phy, x_ref[2] - phz, x_ref) +
-              obstacle_cost<L, U>(a.cp, x.px, x.py, x.pz, obs_lds, a.M, q, tested));
+        S.add(state_cost<L, U>(a.cp, x, x_ref, phx, phy, phz, obs_lds, a.M, q, tested));
 
     for (int ph = 0; ph < nch + 2; ++ph) {
         if (wv == 0) {

@@ -348,29 +348,39 @@ __device__ __forceinline__ float group_sum(float v)
     return v;
 }
 
-// Minimum / maximum over the 64 lanes of the wave (all lanes active), returned in a
-// scalar register: butterflies within each row of 16 (quad permutations, half-row
-// and row mirrors), then the row broadcasts 15 and 31 fold rows into lane 63.
-template <bool kMax, int kCtrl, int kRowMask>
-__device__ __forceinline__ float dpp_extreme_step(float x)
+// Minimum and maximum over the 64 lanes of the wave (all lanes active), returned in
+// scalar registers: butterflies within each row of 16 (quad permutations, half-row and
+// row mirrors), then the row broadcasts 15 and 31 fold rows into lane 63, which alone
+// is read (rows a broadcast does not write keep stale values that never reach lane
+// 63).  The two butterflies run interleaved so that each fills the other's DPP hazard
+// slots.  A NaN lane enters as +inf for the minimum and -inf for the maximum, so it
+// never displaces the other lanes' values.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ float dpp_move(float x)
 {
-    const float y = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x),
-                                                               kCtrl, kRowMask, 0xF, false));
-    // a select, not fmaxf/fminf: no NaN canonicalisation; the caller clamps the bin
-    // indices with fmaxf/fminf, which keeps them in range for any input
-    return kMax ? (y > x ? y : x) : (y < x ? y : x);
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), kCtrl, kRowMask, 0xF, false));
 }
 
-template <bool kMax>
-__device__ __forceinline__ float wave_extreme(float v)
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ void range_step(float& lo, float& hi)
 {
-    v = dpp_extreme_step<kMax, 0xB1, 0xF>(v);     // quad_perm [1, 0, 3, 2]
-    v = dpp_extreme_step<kMax, 0x4E, 0xF>(v);     // quad_perm [2, 3, 0, 1]
-    v = dpp_extreme_step<kMax, 0x141, 0xF>(v);    // row_half_mirror
-    v = dpp_extreme_step<kMax, 0x140, 0xF>(v);    // row_mirror
-    v = dpp_extreme_step<kMax, 0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
-    v = dpp_extreme_step<kMax, 0x143, 0xC>(v);    // row_bcast:31 into rows 2 and 3
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+    const float a = dpp_move<kCtrl, kRowMask>(lo), b = dpp_move<kCtrl, kRowMask>(hi);
+    lo = a < lo ? a : lo;
+    hi = b > hi ? b : hi;
+}
+
+__device__ __forceinline__ void wave_range(float v, float& lo, float& hi)
+{
+    const bool nan = v != v;
+    float a = nan ? INFINITY : v, b = nan ? -INFINITY : v;
+    range_step<0xB1, 0xF>(a, b);     // quad_perm [1, 0, 3, 2]
+    range_step<0x4E, 0xF>(a, b);     // quad_perm [2, 3, 0, 1]
+    range_step<0x141, 0xF>(a, b);    // row_half_mirror
+    range_step<0x140, 0xF>(a, b);    // row_mirror
+    range_step<0x142, 0xA>(a, b);    // row_bcast:15 into rows 1 and 3
+    range_step<0x143, 0xC>(a, b);    // row_bcast:31 into rows 2 and 3
+    lo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a), 63));
+    hi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b), 63));
 }
 
 // Obstacles in LDS, one block per workgroup (see stage_obstacles):
@@ -380,14 +390,22 @@ __device__ __forceinline__ float wave_extreme(float v)
 //     a = (cx, cy, cz, zmask)  centre relative to the frame origin; zmask 0 for a
 //                              vertical cylinder (ignore z), 1 for a sphere
 //     b = (r^2, (r + margin)^2, r + margin, 0)
+//   then kObsPad padding entries a = 0, b = (-inf, -inf, 0, 0), which no distance is
+//   below: obstacle_cost reads up to 2 L max(U, 2) - 1 entries past the last obstacle.
 constexpr int kObsBins = 64;
 constexpr int kObsHeaderFloat4 = 1 + 68 / 4;        // header + padded bin table
+constexpr int kObsPad = 64;                         // >= 2 L max(U, 2) - 1, L <= 8, U <= 4
 constexpr int kCullMin = 16, kCullMax = 512;       // sorted and culled for M in this range
 constexpr float kCullSlack = 1.0e-3f;              // m, covers rounding of the x tests
 
+// float4 slots of the obstacle block (header, bins, obstacles, padding).
+__host__ __device__ constexpr int obstacle_lds_float4(int M)
+{
+    return kObsHeaderFloat4 + 2 * ((M > 0 ? M : 0) + kObsPad);
+}
 __host__ __device__ constexpr size_t obstacle_lds_bytes(int M)
 {
-    return sizeof(float4) * (size_t)(kObsHeaderFloat4 + 2 * (M > 0 ? M : 0));
+    return sizeof(float4) * (size_t)obstacle_lds_float4(M);
 }
 
 // Obstacle term of Eq. (22) (with the quadratic margin) for this lane's position.
@@ -396,6 +414,9 @@ __host__ __device__ constexpr size_t obstacle_lds_bytes(int M)
 // x-range of all its lanes' positions and tests only obstacles whose centre lies
 // within R_max + slack of that range: every other obstacle is farther than its
 // r + margin from every lane, so it adds exactly zero to the penalty and to the hit.
+// Every lane runs the same number of tests, ceil(window / L) rounded up to R = max(U,
+// 2); the indices past the window reach obstacles outside it or the padding, which add
+// exactly zero, so the result is that of testing the window alone, in the same order.
 template <int L, int U>
 __device__ __forceinline__ float obstacle_cost(const CostParams& C, float px, float py, float pz,
                                                const float4* __restrict__ blk, int M, int q,
@@ -403,28 +424,59 @@ __device__ __forceinline__ float obstacle_cost(const CostParams& C, float px, fl
 {
     const float4 h = blk[0];
     const int* bins = reinterpret_cast<const int*>(blk + 1);
-    const float4* obs = blk + kObsHeaderFloat4;
     int i0 = 0, i1 = M;
     if (h.w != 0.0f) {
-        const float lo = wave_extreme<false>(px) - h.z, hi = wave_extreme<true>(px) + h.z;
+        float lo, hi;
+        wave_range(px, lo, hi);
+        lo -= h.z;
+        hi += h.z;
         const float b0 = fminf(fmaxf(floorf((lo - h.x) * h.y), 0.0f), (float)kObsBins);
         const float b1 = fminf(fmaxf(floorf((hi - h.x) * h.y) + 1.0f, 0.0f), (float)kObsBins);
         i0 = __builtin_amdgcn_readfirstlane(bins[(int)b0]);
         i1 = __builtin_amdgcn_readfirstlane(bins[(int)b1]);
     }
-    tested += i1 - i0;                     // obstacles each sample of this wave tests
-    float hit = 0.0f, pen = 0.0f;
-#pragma unroll U
-    for (int i = i0 + q; i < i1; i += L) {
-        const float4 a = obs[2 * i], b = obs[2 * i + 1];
-        const float dx = px - a.x, dy = py - a.y, dz = (pz - a.z) * a.w;
-        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        hit = d2 < b.x ? 1.0f : hit;
-        if (d2 < b.y) {
-            const float gap = b.z - __builtin_amdgcn_sqrtf(d2);
-            pen = fmaf(gap, gap, pen);
+    tested += i1 - i0;                     // obstacles each sample of this wave needs
+    // R register slots, each holding one test's operands: a slot is scored, then
+    // refilled with the test R further on, whose loads are in flight while the other
+    // slots are scored.  Lane's test t reads o[2 L t] and o[2 L t + 1].
+    constexpr int R = U < 2 ? 2 : U;
+    const int n = (i1 - i0 + (L - 1)) / L;                      // tests per lane, uniform
+    const float4* o = blk + kObsHeaderFloat4 + 2 * (i0 + q);
+    // no scalar load may be outstanding when the loop starts: those return out of
+    // order, and with one pending every wait in the loop would be for all LDS loads
+    // rather than for the oldest slot's
+    __builtin_amdgcn_s_waitcnt(0xC07F);                         // lgkmcnt(0) only
+    float4 a[R], b[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        a[r] = o[2 * L * r];
+        b[r] = o[2 * L * r + 1];
+        __builtin_amdgcn_sched_barrier(0);     // issued in slot order, as in the loop
+    }
+    float hits[R], pen = 0.0f;             // a hit flag per slot, so each slot's operands
+#pragma unroll                             // are dead once it has been scored
+    for (int r = 0; r < R; ++r) hits[r] = 0.0f;
+    for (int t = 0; t < n; t += R) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float dx = px - a[r].x, dy = py - a[r].y, dz = (pz - a[r].z) * a[r].w;
+            const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            hits[r] = d2 < b[r].x ? 1.0f : hits[r];
+            if (d2 < b[r].y) {
+                const float gap = b[r].z - __builtin_amdgcn_sqrtf(d2);
+                pen = fmaf(gap, gap, pen);
+            }
+            a[r] = o[2 * L * (t + R + r)];            // index < M + 2 L R - 1 (padding)
+            b[r] = o[2 * L * (t + R + r) + 1];
+            // compiler-only barriers: without them the refill is folded into a load at
+            // the top of the next iteration, or scheduled after the other slots' tests
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
+    float hit = hits[0];
+#pragma unroll
+    for (int r = 1; r < R; ++r) hit = hits[r] > 0.0f ? 1.0f : hit;
     if (L > 1) {
         pen = group_sum<L>(pen);
         hit = group_sum<L>(hit);

@@ -51,6 +51,11 @@ __device__ __forceinline__ void stage_obstacles(float4* blk, const mppi_obstacle
         o_lds[2 * rank + 1] = make_float4(o.r * o.r, R * R, R, 0.0f);
         atomicMax(&s_rmax, __float_as_uint(fmaxf(R, 0.0f)));
     }
+    for (int i = threadIdx.x; i < kObsPad; i += blockDim.x) {
+        const int m = (M > 0 ? M : 0) + i;
+        o_lds[2 * m] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        o_lds[2 * m + 1] = make_float4(-INFINITY, -INFINITY, 0.0f, 0.0f);
+    }
     __syncthreads();
     float x0 = 0.0f, w = 1.0f;
     if (cull) {
@@ -72,6 +77,21 @@ __device__ __forceinline__ void stage_obstacles(float4* blk, const mppi_obstacle
     }
     if (threadIdx.x == 0)
         blk[0] = make_float4(x0, 1.0f / w, __uint_as_float(s_rmax) + kCullSlack, cull ? 1.0f : 0.0f);
+}
+
+// Running cost of a state against reference row ref (Eqs. (17), (18), (22)); the row's
+// loads are issued before the obstacle tests and used after them.
+template <int L, int U>
+__device__ __forceinline__ float state_cost(const CostParams& C, const State& x,
+                                            const float* __restrict__ ref, float phx, float phy,
+                                            float phz, const float4* __restrict__ obs_lds, int M,
+                                            int q, int& tested)
+{
+    float r[13];
+#pragma unroll
+    for (int e = 0; e < 13; ++e) r[e] = ref[e];
+    const float co = obstacle_cost<L, U>(C, x.px, x.py, x.pz, obs_lds, M, q, tested);
+    return tracking_cost(C, x, r[0] - phx, r[1] - phy, r[2] - phz, r) + co;
 }
 
 // Rollout of sample k by lane q of its L lanes.  The L lanes integrate the same
@@ -111,8 +131,7 @@ __device__ __forceinline__ float rollout_sample(const RolloutParams& a, const fl
     KahanSum S;
     int tested = 0;
     // state j = 0 (the estimate itself) is scored like every other state (Eq. (17))
-    S.add(tracking_cost(a.cp, x, x_ref[0] - phx, x_ref[1] - phy, x_ref[2] - phz, x_ref) +
-          obstacle_cost<L, U>(a.cp, x.px, x.py, x.pz, obs_lds, a.M, q, tested));
+    S.add(state_cost<L, U>(a.cp, x, x_ref, phx, phy, phz, obs_lds, a.M, q, tested));
 
     float up[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     // With L lanes per sample the noise is drawn round-robin: at steps j = 0, L, 2L, ...
@@ -157,9 +176,8 @@ __device__ __forceinline__ float rollout_sample(const RolloutParams& a, const fl
         rate_controller(a.mp, x.wx, x.wy, x.wz, u, Tc);
         rk4_step<kLag>(a.mp, x, Tc);
 
-        const float* ref = x_ref + (size_t)13 * (j + 1);
-        const float cx = tracking_cost(a.cp, x, ref[0] - phx, ref[1] - phy, ref[2] - phz, ref) +
-                         obstacle_cost<L, U>(a.cp, x.px, x.py, x.pz, obs_lds, a.M, q, tested);
+        const float cx = state_cost<L, U>(a.cp, x, x_ref + (size_t)13 * (j + 1), phx, phy, phz,
+                                          obs_lds, a.M, q, tested);
         S.add(cu + cx);
 
         if (kDump && writer) {
@@ -272,19 +290,23 @@ __device__ __forceinline__ void pipe_translation_chunk(const RolloutParams& a,
                                                        KahanSum& S, int& tested, int c, int sb,
                                                        int q, const PipeLds& P)
 {
+    float4 h[5];                           // step s's hand-over, loaded during step s - 1
+#pragma unroll
+    for (int e = 0; e < 5; ++e) h[e] = P.r[c & 1][0][e][sb];
     for (int s = 0; s < kPipeChunk; ++s) {
         const int j = c * kPipeChunk + s;
         if (j >= a.N) break;
-        const float4 ax = P.r[c & 1][s][0][sb], ay = P.r[c & 1][s][1][sb];
-        const float4 az = P.r[c & 1][s][2][sb], qv = P.r[c & 1][s][3][sb];
-        const float4 wv = P.r[c & 1][s][4][sb];
+        const float4 ax = h[0], ay = h[1], az = h[2], qv = h[3], wv = h[4];
+        if (s + 1 < kPipeChunk) {
+#pragma unroll
+            for (int e = 0; e < 5; ++e) h[e] = P.r[c & 1][s + 1][e][sb];
+        }
         const StageAccel A{{ax.x, ax.y, ax.z, ax.w}, {ay.x, ay.y, ay.z, ay.w}, {az.x, az.y, az.z, az.w}};
         rk4_translational(a.mp, x, A);
         x.qw = qv.x; x.qx = qv.y; x.qy = qv.z; x.qz = qv.w;
         x.wx = wv.x; x.wy = wv.y; x.wz = wv.z;
-        const float* ref = x_ref + (size_t)13 * (j + 1);
-        const float cx = tracking_cost(a.cp, x, ref[0] - phx, ref[1] - phy, ref[2] - phz, ref) +
-                         obstacle_cost<L, U>(a.cp, x.px, x.py, x.pz, obs_lds, a.M, q, tested);
+        const float cx = state_cost<L, U>(a.cp, x, x_ref + (size_t)13 * (j + 1), phx, phy, phz,
+                                          obs_lds, a.M, q, tested);
         S.add(wv.w + cx);
     }
 }
