@@ -236,10 +236,11 @@ mppi_status mppi_plant_step(mppi_ctx *ctx, void *stream, const mppi_vehicle *veh
  * noise), and one merge launch rescales the partials by exp(-(rho_w - rho)/lambda);
  * fused = 0 stores delta_u and runs the weights and the GEMV-shaped weighted sum.
  * pipe = 1 (M <= 384; either fused value) runs the rollouts wave-specialised: per 64
- * samples one workgroup of 2 + lanes waves -- noise, rotational dynamics, and `lanes`
- * translation-and-cost waves -- handing chunks of steps over through LDS (block is
- * then 64 (2 + lanes) and the field is ignored); same arithmetic, same results as
- * pipe = 0 with the same lanes and unroll, shorter per-step critical path.
+ * samples one workgroup of 4 + lanes waves -- noise, body rates, attitude, translation
+ * and tracking cost, and `lanes` obstacle-cost waves -- handing chunks of steps over
+ * through LDS (block is then 64 (4 + lanes) and the field is ignored); the arithmetic
+ * of pipe = 0 with the same lanes and unroll (costs may differ in the last bits where
+ * the compiler fuses operations differently), with a shorter per-step critical path.
  * Every shape computes the same update up to rounding: the order of the obstacle-
  * penalty additions depends on lanes, and the order of the weighted sums on fused. */
 typedef struct mppi_launch_config {

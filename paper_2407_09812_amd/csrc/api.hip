@@ -513,7 +513,7 @@ mppi_status mppi_autotune(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh, 
             for (int block : {64, 128, 256})
                 for (int unroll : {1, 4}) {
                     if (unroll > 1 && M < 8) continue;
-                    if (pipe && block != 64) continue;   // its workgroup is 64 (2 + lanes)
+                    if (pipe && block != 64) continue;   // its workgroup is 64 (4 + lanes)
                     cands.push_back(LaunchConfig{block, lanes, unroll, fused ? 1 : 0, pipe ? 1 : 0});
                 }
         }

@@ -36,7 +36,7 @@ struct LaunchConfig {
     int lanes;      // 1, 2, 4, 8
     int unroll;     // 1, 4
     int fused = 0;  // 1: single pass (per-wave partial sums), 0: stored delta_u
-    int pipe = 0;   // 1: wave-specialised rollouts (stored delta_u; block is 64 (2 + lanes))
+    int pipe = 0;   // 1: wave-specialised rollouts (block is 64 (4 + lanes))
 };
 
 bool valid_config(const LaunchConfig& c);

@@ -71,13 +71,13 @@ __global__ __launch_bounds__(256) void rollout_fused_kernel(
     }
 }
 
-// Wave-specialised rollouts: one workgroup of 2 + L waves per 64 samples -- noise,
-// rotation, and L translation-and-cost waves -- handing chunks of steps over through
-// LDS; with tail.stat the translation waves write the weight statistics (single pass,
-// kFused: and their partial sums, delta_u not stored) and the last workgroup reduces
-// them.
+// Wave-specialised rollouts of 64 samples per workgroup (roles in stages.h): wave 0
+// noise, wave 1 body rates, wave 2 attitude, wave 3 translation and tracking cost,
+// waves 4 .. 4 + L - 1 obstacles and the running cost.  Obstacles and hand-over buffers live in LDS; with
+// tail.stat the obstacle waves write the weight statistics (single pass, kFused: and
+// their partial sums, delta_u not stored) and the last workgroup reduces them.
 template <int L, int U, bool kLag, bool kFused>
-__global__ __launch_bounds__(64 * (2 + 8)) void rollout_pipe_kernel(
+__global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
     RolloutParams a, const float* __restrict__ x_hat, const float* __restrict__ x_ref,
     const mppi_obstacle* __restrict__ obs, const float* __restrict__ u_nom,
     float* __restrict__ du_out, float* __restrict__ S_out, UpdateTail tail)
@@ -90,9 +90,10 @@ __global__ __launch_bounds__(64 * (2 + 8)) void rollout_pipe_kernel(
     __syncthreads();
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nch = (a.N + kPipeChunk - 1) / kPipeChunk;
+    constexpr int kO = 4;                 // first obstacle wave
     int sb = lane, q = 0;
-    if (wv >= 2) {                        // 64 / L samples per translation wave
-        sb = (wv - 2) * (64 / L) + lane / L;
+    if (wv >= kO) {                       // 64 / L samples per obstacle wave
+        sb = (wv - kO) * (64 / L) + lane / L;
         q = lane % L;
     }
     const int k = blockIdx.x * 64 + sb;
@@ -109,26 +110,31 @@ __global__ __launch_bounds__(64 * (2 + 8)) void rollout_pipe_kernel(
     float up[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     KahanSum S;
     int tested = 0;
-    if (wv >= 2)                           // state j = 0 is scored too (Eq. (17))
-        S.add(state_cost<L, U>(a.cp, x, x_ref, phx, phy, phz, obs_lds, a.M, q, tested));
+    const float4 oh = obs_lds[0];          // obstacle block header
+    if (wv >= kO)                          // state j = 0 is scored too (Eq. (17))
+        S.add(state_cost<L, U>(a.cp, x, x_ref, phx, phy, phz, oh, obs_lds, a.M, q, tested));
 
-    for (int ph = 0; ph < nch + 2; ++ph) {
+    for (int ph = 0; ph < nch + kO; ++ph) {
         if (wv == 0) {
             if (ph < nch) pipe_noise_chunk<!kFused>(a, u_nom, du_out, writer, kk, ph, up, P, lane);
         } else if (wv == 1) {
-            if (ph >= 1 && ph <= nch) pipe_rotation_chunk<kLag>(a, x, ph - 1, P, lane);
-        } else if (ph >= 2) {
-            pipe_translation_chunk<L, U>(a, x_ref, obs_lds, phx, phy, phz, x, S, tested, ph - 2, sb, q, P);
+            if (ph >= 1 && ph < nch + 1) pipe_rates_chunk<kLag>(a, x, ph - 1, P, lane);
+        } else if (wv == 2) {
+            if (ph >= 2 && ph < nch + 2) pipe_attitude_chunk(a, x, ph - 2, P, lane);
+        } else if (wv == 3) {
+            if (ph >= 3 && ph < nch + 3) pipe_translation_chunk(a, x_ref, oh, obs_lds, phx, phy, phz, x, ph - 3, lane, P);
+        } else if (ph >= kO) {
+            pipe_obstacle_chunk<L, U>(a, obs_lds, S, tested, ph - kO, sb, q, P);
         }
         __syncthreads();
     }
-    if (wv >= 2) {
+    if (wv >= kO) {
         if (writer) S_out[k] = S.s;
         if (a.obs_tests) {
             const unsigned long long samples = __popcll(__ballot(writer));
             if (lane == 0) atomicAdd(a.obs_tests, samples * (unsigned long long)tested);
         }
-        const int w = blockIdx.x * L + (wv - 2);
+        const int w = blockIdx.x * L + (wv - kO);
         if (kFused)
             fused_wave_partials<L>(a, tail.lambda, wave_sums(S.s, k, q, valid, tail.lambda), kk, q,
                                    tail.stat + w, tail.part + (size_t)w * 4 * a.N, tail.rho_run);
@@ -300,7 +306,7 @@ static hipError_t launch_pipe_lu(const RolloutArgs& a, const UpdateTail& tail, b
     const RolloutParams p{a.mp, a.cp, a.np, a.M, a.K, a.N, a.ld, a.obs_tests};
     auto kernel = fused ? (a.mp.lag ? rollout_pipe_kernel<L, U, true, true> : rollout_pipe_kernel<L, U, false, true>)
                         : (a.mp.lag ? rollout_pipe_kernel<L, U, true, false> : rollout_pipe_kernel<L, U, false, false>);
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(64 * (2 + L)), pipe_lds_bytes(a.M), stream, p, a.x_hat,
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(64 * (4 + L)), pipe_lds_bytes(a.M), stream, p, a.x_hat,
                        a.x_ref, a.obs, a.u_nom, a.du, a.S, tail);
     return hipGetLastError();
 }

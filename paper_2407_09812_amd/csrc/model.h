@@ -185,34 +185,6 @@ __device__ __forceinline__ Wrench allocate(const ModelParams& P, float T0, float
 
 // Attitude, velocity and body rate: the part of the state the right-hand side of
 // Eq. (6) depends on (it does not depend on the position).
-struct Body {
-    float qw, qx, qy, qz;
-    float vx, vy, vz;
-    float wx, wy, wz;
-};
-
-#define MPPI_ROT_FIELDS(X) X(qw) X(qx) X(qy) X(qz) X(wx) X(wy) X(wz)
-
-__device__ __forceinline__ void body_derivative(const ModelParams& P, const Body& b, const Wrench& W,
-                                                Body& d)
-{
-    // q' = 1/2 q (x) [0, omega]
-    const float hx = 0.5f * b.wx, hy = 0.5f * b.wy, hz = 0.5f * b.wz;
-    d.qw = -(b.qx * hx + b.qy * hy + b.qz * hz);
-    d.qx = b.qw * hx + b.qy * hz - b.qz * hy;
-    d.qy = b.qw * hy - b.qx * hz + b.qz * hx;
-    d.qz = b.qw * hz + b.qx * hy - b.qy * hx;
-    // v' = R(q) [0, 0, F] / m + [0, 0, -g]; third column of R(q)
-    const float fm = W.F * P.m_inv, f2 = fm + fm;
-    d.vx = f2 * (b.qx * b.qz + b.qw * b.qy);
-    d.vy = f2 * (b.qy * b.qz - b.qw * b.qx);
-    d.vz = fm - f2 * (b.qx * b.qx + b.qy * b.qy) - P.g;
-    // omega' = J^-1 (tau - omega x J omega)
-    d.wx = (W.tx - P.G[0] * (b.wy * b.wz)) * P.J_inv[0];
-    d.wy = (W.ty - P.G[1] * (b.wz * b.wx)) * P.J_inv[1];
-    d.wz = (W.tz - P.G[2] * (b.wx * b.wy)) * P.J_inv[2];
-}
-
 // Accelerations v' at the four RK4 stage points of one step.
 struct StageAccel {
     float x[4], y[4], z[4];
@@ -224,61 +196,121 @@ struct StageAccel {
 // linear lag (W(T) + c_s W(T_cmd - T), exact since the allocation is linear), and
 // since nothing depends on the position its update is p + h v + h^2/6 (a1 + a2 + a3),
 // which is what RK4's four stage velocities sum to.  Nothing in the rotational part
-// (q, omega, T) depends on p or v, so the step splits into rk4_rotational, which also
-// returns the stage accelerations, and rk4_translational, which integrates p and v
-// from them.
+// (q, omega, T) depends on p or v, and omega' depends on omega and the thrusts only,
+// so the step splits into three chains: rk4_rates (omega, T), rk4_attitude (q, given
+// the stage rates and thrusts, with the stage accelerations) and rk4_translational
+// (p, v from the stage accelerations).  Values handed from one chain to the next go
+// through opaque(), so every kernel that splits them across waves computes the same.
+
+// Body rates, stage by stage: omega at the four RK4 stage points and the collective
+// thrust there (the rates part of rk4_rotational; omega' depends on omega and the
+// thrusts only).
+struct RateStages {
+    float wx[4], wy[4], wz[4], F[4];
+};
+
 template <bool kLag>
-__device__ __forceinline__ void rk4_rotational(const ModelParams& P, State& x, const float Tc[4],
-                                               StageAccel& A)
+__device__ __forceinline__ void rk4_rates(const ModelParams& P, State& x, const float Tc[4],
+                                          RateStages& R)
 {
     const float h = P.dt, h2 = 0.5f * P.dt, h6 = P.dt * (1.0f / 6.0f);
-    Wrench W1, W2, W3, W4;
+    Wrench Ws[4];
     float D0 = 0.0f, D1 = 0.0f, D2 = 0.0f, D3 = 0.0f;
     if (kLag) {
         D0 = Tc[0] - x.T0; D1 = Tc[1] - x.T1; D2 = Tc[2] - x.T2; D3 = Tc[3] - x.T3;
         const Wrench W0 = allocate(P, x.T0, x.T1, x.T2, x.T3);
         const Wrench dW = allocate(P, D0, D1, D2, D3);
-        W1 = W0;
-#define MPPI_STAGE_WRENCH(Ws, c) \
-        Ws = Wrench{fmaf(c, dW.F, W0.F), fmaf(c, dW.tx, W0.tx), fmaf(c, dW.ty, W0.ty), fmaf(c, dW.tz, W0.tz)};
-        MPPI_STAGE_WRENCH(W2, P.lag_c[0])
-        MPPI_STAGE_WRENCH(W3, P.lag_c[1])
-        MPPI_STAGE_WRENCH(W4, P.lag_c[2])
+        Ws[0] = W0;
+#define MPPI_STAGE_WRENCH(Wd, c) \
+        Wd = Wrench{fmaf(c, dW.F, W0.F), fmaf(c, dW.tx, W0.tx), fmaf(c, dW.ty, W0.ty), fmaf(c, dW.tz, W0.tz)};
+        MPPI_STAGE_WRENCH(Ws[1], P.lag_c[0])
+        MPPI_STAGE_WRENCH(Ws[2], P.lag_c[1])
+        MPPI_STAGE_WRENCH(Ws[3], P.lag_c[2])
 #undef MPPI_STAGE_WRENCH
     } else {
-        W1 = W2 = W3 = W4 = allocate(P, Tc[0], Tc[1], Tc[2], Tc[3]);
+        Ws[0] = Ws[1] = Ws[2] = Ws[3] = allocate(P, Tc[0], Tc[1], Tc[2], Tc[3]);
     }
-    const Body b{x.qw, x.qx, x.qy, x.qz, x.vx, x.vy, x.vz, x.wx, x.wy, x.wz};
-    Body k, bs, acc;
-    body_derivative(P, b, W1, k);                                // k1
-    A.x[0] = opaque(k.vx); A.y[0] = opaque(k.vy); A.z[0] = opaque(k.vz);
-#define STAGE1(f) acc.f = k.f; bs.f = fmaf(h2, k.f, b.f);
-    MPPI_ROT_FIELDS(STAGE1)
-#undef STAGE1
-    body_derivative(P, bs, W2, k);                               // k2
-    A.x[1] = opaque(k.vx); A.y[1] = opaque(k.vy); A.z[1] = opaque(k.vz);
-#define STAGE2(f) acc.f = fmaf(2.0f, k.f, acc.f); bs.f = fmaf(h2, k.f, b.f);
-    MPPI_ROT_FIELDS(STAGE2)
-#undef STAGE2
-    body_derivative(P, bs, W3, k);                               // k3
-    A.x[2] = opaque(k.vx); A.y[2] = opaque(k.vy); A.z[2] = opaque(k.vz);
-#define STAGE3(f) acc.f = fmaf(2.0f, k.f, acc.f); bs.f = fmaf(h, k.f, b.f);
-    MPPI_ROT_FIELDS(STAGE3)
-#undef STAGE3
-    body_derivative(P, bs, W4, k);                               // k4
-    A.x[3] = opaque(k.vx); A.y[3] = opaque(k.vy); A.z[3] = opaque(k.vz);
-#define STAGE4(f) x.f = fmaf(h6, acc.f + k.f, b.f);
-    MPPI_ROT_FIELDS(STAGE4)
-#undef STAGE4
-    const float n2 = x.qw * x.qw + x.qx * x.qx + x.qy * x.qy + x.qz * x.qz;
-    const float inv = __builtin_amdgcn_rsqf(n2);
-    x.qw *= inv; x.qx *= inv; x.qy *= inv; x.qz *= inv;
+    const float bx = x.wx, by = x.wy, bz = x.wz;
+    float sx = bx, sy = by, sz = bz, ax = 0.0f, ay = 0.0f, az = 0.0f;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        sx = opaque(sx); sy = opaque(sy); sz = opaque(sz);
+        R.wx[s] = sx; R.wy[s] = sy; R.wz[s] = sz;
+        R.F[s] = opaque(Ws[s].F);
+        // omega' = J^-1 (tau - omega x J omega)
+        const float kx = (Ws[s].tx - P.G[0] * (sy * sz)) * P.J_inv[0];
+        const float ky = (Ws[s].ty - P.G[1] * (sz * sx)) * P.J_inv[1];
+        const float kz = (Ws[s].tz - P.G[2] * (sx * sy)) * P.J_inv[2];
+        if (s == 0) {
+            ax = kx; ay = ky; az = kz;
+            sx = fmaf(h2, kx, bx); sy = fmaf(h2, ky, by); sz = fmaf(h2, kz, bz);
+        } else if (s == 1) {
+            ax = fmaf(2.0f, kx, ax); ay = fmaf(2.0f, ky, ay); az = fmaf(2.0f, kz, az);
+            sx = fmaf(h2, kx, bx); sy = fmaf(h2, ky, by); sz = fmaf(h2, kz, bz);
+        } else if (s == 2) {
+            ax = fmaf(2.0f, kx, ax); ay = fmaf(2.0f, ky, ay); az = fmaf(2.0f, kz, az);
+            sx = fmaf(h, kx, bx); sy = fmaf(h, ky, by); sz = fmaf(h, kz, bz);
+        } else {
+            x.wx = fmaf(h6, ax + kx, bx); x.wy = fmaf(h6, ay + ky, by); x.wz = fmaf(h6, az + kz, bz);
+        }
+    }
     if (kLag) {
         x.T0 = fmaf(P.lag_c[3], D0, x.T0); x.T1 = fmaf(P.lag_c[3], D1, x.T1);
         x.T2 = fmaf(P.lag_c[3], D2, x.T2); x.T3 = fmaf(P.lag_c[3], D3, x.T3);
     } else {
         x.T0 = Tc[0]; x.T1 = Tc[1]; x.T2 = Tc[2]; x.T3 = Tc[3];
     }
+}
+
+// Attitude over one step from the stage rates and thrusts of rk4_rates, with the stage
+// accelerations v' = R(q) [0, 0, F] / m + [0, 0, -g]; then q <- q / |q|.
+__device__ __forceinline__ void rk4_attitude(const ModelParams& P, State& x, const RateStages& R,
+                                             StageAccel& A)
+{
+    const float h = P.dt, h2 = 0.5f * P.dt, h6 = P.dt * (1.0f / 6.0f);
+    const float bw = x.qw, bx = x.qx, by = x.qy, bz = x.qz;
+    float qw = bw, qx = bx, qy = by, qz = bz;
+    float aw = 0.0f, ax = 0.0f, ay = 0.0f, az = 0.0f;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        // q' = 1/2 q (x) [0, omega]
+        const float hx = 0.5f * R.wx[s], hy = 0.5f * R.wy[s], hz = 0.5f * R.wz[s];
+        const float kw = -(qx * hx + qy * hy + qz * hz);
+        const float kx = qw * hx + qy * hz - qz * hy;
+        const float ky = qw * hy - qx * hz + qz * hx;
+        const float kz = qw * hz + qx * hy - qy * hx;
+        // third column of R(q)
+        const float fm = R.F[s] * P.m_inv, f2 = fm + fm;
+        A.x[s] = opaque(f2 * (qx * qz + qw * qy));
+        A.y[s] = opaque(f2 * (qy * qz - qw * qx));
+        A.z[s] = opaque(fm - f2 * (qx * qx + qy * qy) - P.g);
+        if (s == 0) {
+            aw = kw; ax = kx; ay = ky; az = kz;
+            qw = fmaf(h2, kw, bw); qx = fmaf(h2, kx, bx); qy = fmaf(h2, ky, by); qz = fmaf(h2, kz, bz);
+        } else if (s == 1) {
+            aw = fmaf(2.0f, kw, aw); ax = fmaf(2.0f, kx, ax); ay = fmaf(2.0f, ky, ay); az = fmaf(2.0f, kz, az);
+            qw = fmaf(h2, kw, bw); qx = fmaf(h2, kx, bx); qy = fmaf(h2, ky, by); qz = fmaf(h2, kz, bz);
+        } else if (s == 2) {
+            aw = fmaf(2.0f, kw, aw); ax = fmaf(2.0f, kx, ax); ay = fmaf(2.0f, ky, ay); az = fmaf(2.0f, kz, az);
+            qw = fmaf(h, kw, bw); qx = fmaf(h, kx, bx); qy = fmaf(h, ky, by); qz = fmaf(h, kz, bz);
+        } else {
+            x.qw = fmaf(h6, aw + kw, bw); x.qx = fmaf(h6, ax + kx, bx);
+            x.qy = fmaf(h6, ay + ky, by); x.qz = fmaf(h6, az + kz, bz);
+        }
+    }
+    const float n2 = x.qw * x.qw + x.qx * x.qx + x.qy * x.qy + x.qz * x.qz;
+    const float inv = __builtin_amdgcn_rsqf(n2);
+    x.qw *= inv; x.qx *= inv; x.qy *= inv; x.qz *= inv;
+}
+
+// The rotational half of the step: body rates and thrusts, then the attitude.
+template <bool kLag>
+__device__ __forceinline__ void rk4_rotational(const ModelParams& P, State& x, const float Tc[4],
+                                               StageAccel& A)
+{
+    RateStages R;
+    rk4_rates<kLag>(P, x, Tc, R);
+    rk4_attitude(P, x, R, A);
 }
 
 // p and v over the step from the stage accelerations of rk4_rotational.
@@ -408,8 +440,8 @@ __host__ __device__ constexpr size_t obstacle_lds_bytes(int M)
     return sizeof(float4) * (size_t)obstacle_lds_float4(M);
 }
 
-// Obstacle term of Eq. (22) (with the quadratic margin) for this lane's position.
-// Lane q of a sample's L lanes tests obstacles q, q + L, ...; the partial penalties and
+// Obstacle term of Eq. (22) (with the quadratic margin) for this lane's position; h is
+// the block's header.  Lane q of a sample's L lanes tests obstacles q, q + L, ...; the partial penalties and
 // hit flags are combined over the group.  With culling on, the wave first takes the
 // x-range of all its lanes' positions and tests only obstacles whose centre lies
 // within R_max + slack of that range: every other obstacle is farther than its
@@ -417,14 +449,14 @@ __host__ __device__ constexpr size_t obstacle_lds_bytes(int M)
 // Every lane runs the same number of tests, ceil(window / L) rounded up to R = max(U,
 // 2); the indices past the window reach obstacles outside it or the padding, which add
 // exactly zero, so the result is that of testing the window alone, in the same order.
-template <int L, int U>
-__device__ __forceinline__ float obstacle_cost(const CostParams& C, float px, float py, float pz,
-                                               const float4* __restrict__ blk, int M, int q,
-                                               int& tested)
+// The culling window [i0, i1) for the positions px of the wave's lanes (all active),
+// from the block's header h (read once by the caller).
+__device__ __forceinline__ void obstacle_window(const float4 h, const float4* __restrict__ blk,
+                                                float px, int M, int& i0, int& i1)
 {
-    const float4 h = blk[0];
     const int* bins = reinterpret_cast<const int*>(blk + 1);
-    int i0 = 0, i1 = M;
+    i0 = 0;
+    i1 = M;
     if (h.w != 0.0f) {
         float lo, hi;
         wave_range(px, lo, hi);
@@ -435,7 +467,16 @@ __device__ __forceinline__ float obstacle_cost(const CostParams& C, float px, fl
         i0 = __builtin_amdgcn_readfirstlane(bins[(int)b0]);
         i1 = __builtin_amdgcn_readfirstlane(bins[(int)b1]);
     }
-    tested += i1 - i0;                     // obstacles each sample of this wave needs
+}
+
+// The tests of obstacles [i0, i1) (uniform over the wave): any window that contains the
+// culling window of every lane in the wave gives the same result.
+template <int L, int U>
+__device__ __forceinline__ float obstacle_tests(const CostParams& C, float px, float py, float pz,
+                                                const float4* __restrict__ blk, int i0, int i1, int q,
+                                                int& tested)
+{
+    tested += i1 - i0;                     // obstacles each sample of this wave tests
     // R register slots, each holding one test's operands: a slot is scored, then
     // refilled with the test R further on, whose loads are in flight while the other
     // slots are scored.  Lane's test t reads o[2 L t] and o[2 L t + 1].
@@ -482,6 +523,16 @@ __device__ __forceinline__ float obstacle_cost(const CostParams& C, float px, fl
         hit = group_sum<L>(hit);
     }
     return fmaf(C.w_obs, pen, hit > 0.0f ? C.c_col : 0.0f);
+}
+
+template <int L, int U>
+__device__ __forceinline__ float obstacle_cost(const CostParams& C, const float4 h, float px, float py,
+                                               float pz, const float4* __restrict__ blk, int M, int q,
+                                               int& tested)
+{
+    int i0, i1;
+    obstacle_window(h, blk, px, M, i0, i1);
+    return obstacle_tests<L, U>(C, px, py, pz, blk, i0, i1, q, tested);
 }
 
 // Kahan-compensated accumulation of the rollout cost.

@@ -84,13 +84,14 @@ __device__ __forceinline__ void stage_obstacles(float4* blk, const mppi_obstacle
 template <int L, int U>
 __device__ __forceinline__ float state_cost(const CostParams& C, const State& x,
                                             const float* __restrict__ ref, float phx, float phy,
-                                            float phz, const float4* __restrict__ obs_lds, int M,
-                                            int q, int& tested)
+                                            float phz, const float4 oh,
+                                            const float4* __restrict__ obs_lds, int M, int q,
+                                            int& tested)
 {
     float r[13];
 #pragma unroll
     for (int e = 0; e < 13; ++e) r[e] = ref[e];
-    const float co = obstacle_cost<L, U>(C, x.px, x.py, x.pz, obs_lds, M, q, tested);
+    const float co = obstacle_cost<L, U>(C, oh, x.px, x.py, x.pz, obs_lds, M, q, tested);
     return tracking_cost(C, x, r[0] - phx, r[1] - phy, r[2] - phz, r) + co;
 }
 
@@ -130,8 +131,9 @@ __device__ __forceinline__ float rollout_sample(const RolloutParams& a, const fl
 
     KahanSum S;
     int tested = 0;
+    const float4 oh = obs_lds[0];          // obstacle block header
     // state j = 0 (the estimate itself) is scored like every other state (Eq. (17))
-    S.add(state_cost<L, U>(a.cp, x, x_ref, phx, phy, phz, obs_lds, a.M, q, tested));
+    S.add(state_cost<L, U>(a.cp, x, x_ref, phx, phy, phz, oh, obs_lds, a.M, q, tested));
 
     float up[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     // With L lanes per sample the noise is drawn round-robin: at steps j = 0, L, 2L, ...
@@ -177,7 +179,7 @@ __device__ __forceinline__ float rollout_sample(const RolloutParams& a, const fl
         rk4_step<kLag>(a.mp, x, Tc);
 
         const float cx = state_cost<L, U>(a.cp, x, x_ref + (size_t)13 * (j + 1), phx, phy, phz,
-                                          obs_lds, a.M, q, tested);
+                                          oh, obs_lds, a.M, q, tested);
         S.add(cu + cx);
 
         if (kDump && writer) {
@@ -197,16 +199,19 @@ __device__ __forceinline__ float rollout_sample(const RolloutParams& a, const fl
 }
 
 // ---------------------------------------------------------------------------
-// Wave-specialised rollouts: one workgroup per 64 samples, 2 + L waves.  Nothing in
-// the rotational part of a step (q, omega, rotor thrusts) depends on p or v, so the
-// step's work is split across waves that run on different SIMDs: wave 0 draws the
-// noise and forms u and the input costs, wave 1 runs the controller and the rotational
-// RK4 and hands over the stage accelerations and the new attitude and rates, and waves
-// 2 .. 2 + L - 1 integrate p and v and score the state (L lanes per sample dividing
-// the obstacle tests, as in rollout_sample).  The roles hand over chunks of kPipeChunk
-// steps through double-buffered LDS, one workgroup barrier per chunk, each role one
-// chunk behind the previous.  The arithmetic is rollout_sample's, operation for
-// operation, so the results are the same.
+// Wave-specialised rollouts: one workgroup per 64 samples, 4 + L waves.  The chains
+// of a step depend on one another in one direction only: the body rates and rotor
+// thrusts (rk4_rates) on u alone, the attitude (rk4_attitude) on the stage rates and
+// thrusts, p and v (rk4_translational) on the stage accelerations, and the obstacle
+// term on p.  So the step is split across waves that run on different SIMDs: wave 0
+// draws the noise and forms u and the input costs, wave 1 runs the controller and the
+// rates, wave 2 the attitude and the stage accelerations, wave 3 integrates p and v
+// and scores the tracking cost, and waves 4 .. 4 + L - 1 score the obstacles and sum
+// the running cost (L lanes per sample dividing the obstacle tests, as in
+// rollout_sample).  The roles hand over chunks of kPipeChunk steps through
+// double-buffered LDS, one workgroup barrier per chunk, each role one chunk behind the
+// previous.  The arithmetic is rollout_sample's, operation for operation (the values
+// handed between chains pass through opaque() in both).
 // ---------------------------------------------------------------------------
 
 constexpr int kPipeChunk = 4;
@@ -214,7 +219,11 @@ constexpr int kPipeChunk = 4;
 struct PipeLds {
     float4 u[2][kPipeChunk][64];         // u_j per sample
     float cu[2][kPipeChunk][64];         // input and input-change cost of step j
-    float4 r[2][kPipeChunk][5][64];      // a.x, a.y, a.z (4 stages each), q, (omega, cost)
+    float4 w[2][kPipeChunk][5][64];      // stage rates x, y, z, stage thrust F, (omega, cost)
+    float4 r[2][kPipeChunk][5][64];      // stage accelerations x, y, z, q, (omega, cost)
+    float4 p[2][kPipeChunk][64];         // p_{j+1} relative to p_hat, tracking cost
+    int2 win[2][kPipeChunk];             // culling window of p_{j+1} over the 64 samples
+    float cu_fwd[2][kPipeChunk][64];     // input cost, forwarded to the obstacle role
 };
 
 __host__ __device__ constexpr size_t pipe_lds_bytes(int M)
@@ -258,10 +267,11 @@ __device__ __forceinline__ void pipe_noise_chunk(const RolloutParams& a, const f
     }
 }
 
-// Rotation role: chunk c (x holds q, omega and the rotor thrusts).
+// Rates role: chunk c (x holds omega and the rotor thrusts): the controller, then
+// the body rates and thrusts at the stage points.
 template <bool kLag>
-__device__ __forceinline__ void pipe_rotation_chunk(const RolloutParams& a, State& x, int c, PipeLds& P,
-                                                    int lane)
+__device__ __forceinline__ void pipe_rates_chunk(const RolloutParams& a, State& x, int c, PipeLds& P,
+                                                 int lane)
 {
     for (int s = 0; s < kPipeChunk; ++s) {
         const int j = c * kPipeChunk + s;
@@ -270,44 +280,100 @@ __device__ __forceinline__ void pipe_rotation_chunk(const RolloutParams& a, Stat
         const float u[4] = {uv.x, uv.y, uv.z, uv.w};
         float Tc[4];
         rate_controller(a.mp, x.wx, x.wy, x.wz, u, Tc);
+        RateStages R;
+        rk4_rates<kLag>(a.mp, x, Tc, R);
+        P.w[c & 1][s][0][lane] = make_float4(R.wx[0], R.wx[1], R.wx[2], R.wx[3]);
+        P.w[c & 1][s][1][lane] = make_float4(R.wy[0], R.wy[1], R.wy[2], R.wy[3]);
+        P.w[c & 1][s][2][lane] = make_float4(R.wz[0], R.wz[1], R.wz[2], R.wz[3]);
+        P.w[c & 1][s][3][lane] = make_float4(R.F[0], R.F[1], R.F[2], R.F[3]);
+        P.w[c & 1][s][4][lane] = make_float4(x.wx, x.wy, x.wz, P.cu[c & 1][s][lane]);
+    }
+}
+
+// Attitude role: chunk c (x holds q): q over the step from the stage rates and
+// thrusts, and the stage accelerations.
+__device__ __forceinline__ void pipe_attitude_chunk(const RolloutParams& a, State& x, int c, PipeLds& P,
+                                                    int lane)
+{
+    for (int s = 0; s < kPipeChunk; ++s) {
+        const int j = c * kPipeChunk + s;
+        if (j >= a.N) break;
+        const float4 wx = P.w[c & 1][s][0][lane], wy = P.w[c & 1][s][1][lane];
+        const float4 wz = P.w[c & 1][s][2][lane], F = P.w[c & 1][s][3][lane];
+        const RateStages R{{wx.x, wx.y, wx.z, wx.w}, {wy.x, wy.y, wy.z, wy.w},
+                           {wz.x, wz.y, wz.z, wz.w}, {F.x, F.y, F.z, F.w}};
         StageAccel A;
-        rk4_rotational<kLag>(a.mp, x, Tc, A);
+        rk4_attitude(a.mp, x, R, A);
         P.r[c & 1][s][0][lane] = make_float4(A.x[0], A.x[1], A.x[2], A.x[3]);
         P.r[c & 1][s][1][lane] = make_float4(A.y[0], A.y[1], A.y[2], A.y[3]);
         P.r[c & 1][s][2][lane] = make_float4(A.z[0], A.z[1], A.z[2], A.z[3]);
         P.r[c & 1][s][3][lane] = make_float4(x.qw, x.qx, x.qy, x.qz);
-        P.r[c & 1][s][4][lane] = make_float4(x.wx, x.wy, x.wz, P.cu[c & 1][s][lane]);
+        P.r[c & 1][s][4][lane] = P.w[c & 1][s][4][lane];
     }
 }
 
-// Translation and cost role: chunk c for the sample at position sb of the workgroup,
-// lane q of its L lanes (x holds p relative to p_hat, and v).
-template <int L, int U>
+// Translation role: chunk c of sample `lane` (x holds p relative to p_hat, and v):
+// integrates p and v with the hand-over of the attitude role, scores the tracking cost
+// and takes the culling window of the workgroup's 64 positions (it contains the window
+// of every obstacle wave, so their tests give the same terms); hands p, that cost, the
+// input cost and the window on to the obstacle role.
 __device__ __forceinline__ void pipe_translation_chunk(const RolloutParams& a,
                                                        const float* __restrict__ x_ref,
+                                                       const float4 oh,
                                                        const float4* __restrict__ obs_lds,
                                                        float phx, float phy, float phz, State& x,
-                                                       KahanSum& S, int& tested, int c, int sb,
-                                                       int q, const PipeLds& P)
+                                                       int c, int lane, PipeLds& P)
 {
     float4 h[5];                           // step s's hand-over, loaded during step s - 1
 #pragma unroll
-    for (int e = 0; e < 5; ++e) h[e] = P.r[c & 1][0][e][sb];
+    for (int e = 0; e < 5; ++e) h[e] = P.r[c & 1][0][e][lane];
     for (int s = 0; s < kPipeChunk; ++s) {
         const int j = c * kPipeChunk + s;
         if (j >= a.N) break;
         const float4 ax = h[0], ay = h[1], az = h[2], qv = h[3], wv = h[4];
         if (s + 1 < kPipeChunk) {
 #pragma unroll
-            for (int e = 0; e < 5; ++e) h[e] = P.r[c & 1][s + 1][e][sb];
+            for (int e = 0; e < 5; ++e) h[e] = P.r[c & 1][s + 1][e][lane];
         }
         const StageAccel A{{ax.x, ax.y, ax.z, ax.w}, {ay.x, ay.y, ay.z, ay.w}, {az.x, az.y, az.z, az.w}};
         rk4_translational(a.mp, x, A);
         x.qw = qv.x; x.qx = qv.y; x.qy = qv.z; x.qz = qv.w;
         x.wx = wv.x; x.wy = wv.y; x.wz = wv.z;
-        const float cx = state_cost<L, U>(a.cp, x, x_ref + (size_t)13 * (j + 1), phx, phy, phz,
-                                          obs_lds, a.M, q, tested);
-        S.add(wv.w + cx);
+        const float* ref = x_ref + (size_t)13 * (j + 1);
+        const float tr = tracking_cost(a.cp, x, ref[0] - phx, ref[1] - phy, ref[2] - phz, ref);
+        int i0, i1;
+        obstacle_window(oh, obs_lds, x.px, a.M, i0, i1);
+        P.p[c & 1][s][lane] = make_float4(x.px, x.py, x.pz, tr);
+        P.cu_fwd[c & 1][s][lane] = wv.w;
+        if (lane == 0) P.win[c & 1][s] = make_int2(i0, i1);
+    }
+}
+
+// Obstacle role: chunk c for the sample at position sb of the workgroup, lane q of its
+// L lanes: the obstacle term at the handed-over position, and the running cost in the
+// order of rollout_sample, cu + (tracking + obstacle).
+template <int L, int U>
+__device__ __forceinline__ void pipe_obstacle_chunk(const RolloutParams& a,
+                                                    const float4* __restrict__ obs_lds,
+                                                    KahanSum& S, int& tested, int c, int sb, int q,
+                                                    const PipeLds& P)
+{
+    float4 h = P.p[c & 1][0][sb];
+    float cu = P.cu_fwd[c & 1][0][sb];
+    for (int s = 0; s < kPipeChunk; ++s) {
+        const int j = c * kPipeChunk + s;
+        if (j >= a.N) break;
+        const float4 pt = h;
+        const float cj = cu;
+        if (s + 1 < kPipeChunk) {
+            h = P.p[c & 1][s + 1][sb];
+            cu = P.cu_fwd[c & 1][s + 1][sb];
+        }
+        const int2 win = P.win[c & 1][s];
+        const float co = obstacle_tests<L, U>(a.cp, pt.x, pt.y, pt.z, obs_lds,
+                                              __builtin_amdgcn_readfirstlane(win.x),
+                                              __builtin_amdgcn_readfirstlane(win.y), q, tested);
+        S.add(cj + (pt.w + co));
     }
 }
 

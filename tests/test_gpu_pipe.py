@@ -1,13 +1,16 @@
-"""Wave-specialised rollouts (launch shape pipe = 1): noise, rotational dynamics and
-translation-with-costs on different waves of a workgroup, handing chunks of steps
-over through LDS.  The arithmetic is the one-wave kernel's operation for operation;
-the compiler's fusion of multiplies into adds still differs between the two kernels
-at a few places, so costs agree to the last unit or two of binary32.  Bars, for every
-lane count and unroll, ragged K and N not a multiple of the chunk: the perturbations
-bit for bit; the costs within 1e-5 relative (a state on an obstacle surface may flip
-the collision indicator: then a whole multiple of the collision constant); the whole
-update within 1e-4 (sigma floors); the obstacle-test count exactly; and the oracle at
-1e-4 on one shape.
+"""Wave-specialised rollouts (launch shape pipe = 1): noise, body rates, attitude,
+translation with the tracking cost, and obstacle costs on different waves of a
+workgroup, handing chunks of steps over through LDS.  The arithmetic is the one-wave
+kernel's operation for operation; the compiler's fusion of multiplies into adds still
+differs between the two kernels at a few places, and the obstacle waves take the
+culling window of all 64 samples of the workgroup (which contains each wave's window,
+and so changes which lane of a sample tests which obstacle), so costs agree to the
+last unit or two of binary32.  Bars, for every lane count and unroll, ragged K and N
+not a multiple of the chunk: the perturbations bit for bit; the costs within 1e-5
+relative (a state on an obstacle surface may flip the collision indicator: then a
+whole multiple of the collision constant); the whole update within 1e-4 (sigma
+floors); at least the one-wave kernel's obstacle-test count, the same in both pipe
+variants; and the oracle at 1e-4 on one shape.
 """
 import numpy as np
 import pytest
@@ -87,7 +90,7 @@ def test_pipe_equals_one_wave_kernel_bitwise(lib, ctx, scene):
                   f"{e_S:.1e}, flips {int(flip.sum())}), update {e_u:.1e}, applied {e_a:.1e}, "
                   f"obstacle tests {a[3]} / {b[3]}")
             assert e_S <= 1e-5 and flip.sum() <= 2 and e_u <= TOL and e_a <= TOL
-            assert a[3] == b[3]
+            assert b[3] >= a[3]
             # single pass, both kernels
             f0 = update(lib, ctx, P, lanes, unroll, 0, 1)
             f1 = update(lib, ctx, P, lanes, unroll, 1, 1)
@@ -96,7 +99,7 @@ def test_pipe_equals_one_wave_kernel_bitwise(lib, ctx, scene):
             e_s = rel_err(f1[0].view(-1, 4).double().cpu().numpy(),
                           a[0].view(-1, 4).double().cpu().numpy(), sigma).max()
             print(f"   single pass: pipe vs one-wave {e_f:.1e}, vs stored {e_s:.1e}")
-            assert e_f <= TOL and e_s <= TOL and f1[3] == a[3]
+            assert e_f <= TOL and e_s <= TOL and f0[3] == a[3] and f1[3] == b[3]
 
 
 def test_pipe_rollouts_match_oracle(lib, ctx, orc):
