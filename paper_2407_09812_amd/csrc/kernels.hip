@@ -88,7 +88,7 @@ __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
     const float phx = x_hat[0], phy = x_hat[1], phz = x_hat[2];
     stage_obstacles(obs_lds, obs, a.M, phx, phy, phz, a.cp.margin);
     __syncthreads();
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int nch = (a.N + kPipeChunk - 1) / kPipeChunk;
     constexpr int kO = 4;                 // first obstacle wave
     int sb = lane, q = 0;
@@ -114,19 +114,36 @@ __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
     if (wv >= kO)                          // state j = 0 is scored too (Eq. (17))
         S.add(state_cost<L, U>(a.cp, x, x_ref, phx, phy, phz, oh, obs_lds, a.M, q, tested));
 
-    for (int ph = 0; ph < nch + kO; ++ph) {
-        if (wv == 0) {
+    // Each role runs its own loop over the nch + kO phases, with one workgroup barrier
+    // per phase in every loop (the barrier counts waves, not code locations), so that
+    // only the role's own parameters are live in its loop.
+    const int nph = nch + kO;
+    if (wv == 0) {
+        for (int ph = 0; ph < nph; ++ph) {
             if (ph < nch) pipe_noise_chunk<!kFused>(a, u_nom, du_out, writer, kk, ph, up, P, lane);
-        } else if (wv == 1) {
-            if (ph >= 1 && ph < nch + 1) pipe_rates_chunk<kLag>(a, x, ph - 1, P, lane);
-        } else if (wv == 2) {
-            if (ph >= 2 && ph < nch + 2) pipe_attitude_chunk(a, x, ph - 2, P, lane);
-        } else if (wv == 3) {
-            if (ph >= 3 && ph < nch + 3) pipe_translation_chunk(a, x_ref, oh, obs_lds, phx, phy, phz, x, ph - 3, lane, P);
-        } else if (ph >= kO) {
-            pipe_obstacle_chunk<L, U>(a, obs_lds, S, tested, ph - kO, sb, q, P);
+            __syncthreads();
         }
-        __syncthreads();
+    } else if (wv == 1) {
+        for (int ph = 0; ph < nph; ++ph) {
+            if (ph >= 1 && ph < nch + 1) pipe_rates_chunk<kLag>(a, x, ph - 1, P, lane);
+            __syncthreads();
+        }
+    } else if (wv == 2) {
+        for (int ph = 0; ph < nph; ++ph) {
+            if (ph >= 2 && ph < nch + 2) pipe_attitude_chunk(a, x, ph - 2, P, lane);
+            __syncthreads();
+        }
+    } else if (wv == 3) {
+        for (int ph = 0; ph < nph; ++ph) {
+            if (ph >= 3 && ph < nch + 3)
+                pipe_translation_chunk(a, x_ref, oh, obs_lds, phx, phy, phz, x, ph - 3, lane, P);
+            __syncthreads();
+        }
+    } else {
+        for (int ph = 0; ph < nph; ++ph) {
+            if (ph >= kO) pipe_obstacle_chunk<L, U>(a, obs_lds, S, tested, ph - kO, sb, q, P);
+            __syncthreads();
+        }
     }
     if (wv >= kO) {
         if (writer) S_out[k] = S.s;

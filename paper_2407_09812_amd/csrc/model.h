@@ -450,13 +450,15 @@ __host__ __device__ constexpr size_t obstacle_lds_bytes(int M)
 // 2); the indices past the window reach obstacles outside it or the padding, which add
 // exactly zero, so the result is that of testing the window alone, in the same order.
 // The culling window [i0, i1) for the positions px of the wave's lanes (all active),
-// from the block's header h (read once by the caller).
-__device__ __forceinline__ void obstacle_window(const float4 h, const float4* __restrict__ blk,
-                                                float px, int M, int& i0, int& i1)
+// from the block's header h (read once by the caller).  obstacle_bins issues the bin
+// reads and leaves their values in registers (uniform across the wave), so that a
+// caller can do other work before obstacle_window's readfirstlane waits for them.
+__device__ __forceinline__ void obstacle_bins(const float4 h, const float4* __restrict__ blk,
+                                              float px, int M, int& v0, int& v1)
 {
     const int* bins = reinterpret_cast<const int*>(blk + 1);
-    i0 = 0;
-    i1 = M;
+    v0 = 0;
+    v1 = M;
     if (h.w != 0.0f) {
         float lo, hi;
         wave_range(px, lo, hi);
@@ -464,9 +466,18 @@ __device__ __forceinline__ void obstacle_window(const float4 h, const float4* __
         hi += h.z;
         const float b0 = fminf(fmaxf(floorf((lo - h.x) * h.y), 0.0f), (float)kObsBins);
         const float b1 = fminf(fmaxf(floorf((hi - h.x) * h.y) + 1.0f, 0.0f), (float)kObsBins);
-        i0 = __builtin_amdgcn_readfirstlane(bins[(int)b0]);
-        i1 = __builtin_amdgcn_readfirstlane(bins[(int)b1]);
+        v0 = bins[(int)b0];
+        v1 = bins[(int)b1];
     }
+}
+
+__device__ __forceinline__ void obstacle_window(const float4 h, const float4* __restrict__ blk,
+                                                float px, int M, int& i0, int& i1)
+{
+    int v0, v1;
+    obstacle_bins(h, blk, px, M, v0, v1);
+    i0 = __builtin_amdgcn_readfirstlane(v0);
+    i1 = __builtin_amdgcn_readfirstlane(v1);
 }
 
 // The tests of obstacles [i0, i1) (uniform over the wave): any window that contains the

@@ -339,10 +339,11 @@ __device__ __forceinline__ void pipe_translation_chunk(const RolloutParams& a,
         rk4_translational(a.mp, x, A);
         x.qw = qv.x; x.qx = qv.y; x.qy = qv.z; x.qz = qv.w;
         x.wx = wv.x; x.wy = wv.y; x.wz = wv.z;
-        const float* ref = x_ref + (size_t)13 * (j + 1);
-        const float tr = tracking_cost(a.cp, x, ref[0] - phx, ref[1] - phy, ref[2] - phz, ref);
-        int i0, i1;
-        obstacle_window(oh, obs_lds, x.px, a.M, i0, i1);
+        int v0, v1;                        // bin reads in flight during the tracking cost
+        obstacle_bins(oh, obs_lds, x.px, a.M, v0, v1);
+        const float* rf = x_ref + (size_t)13 * (j + 1);
+        const float tr = tracking_cost(a.cp, x, rf[0] - phx, rf[1] - phy, rf[2] - phz, rf);
+        const int i0 = __builtin_amdgcn_readfirstlane(v0), i1 = __builtin_amdgcn_readfirstlane(v1);
         P.p[c & 1][s][lane] = make_float4(x.px, x.py, x.pz, tr);
         P.cu_fwd[c & 1][s][lane] = wv.w;
         if (lane == 0) P.win[c & 1][s] = make_int2(i0, i1);
