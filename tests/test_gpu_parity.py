@@ -307,6 +307,26 @@ def test_full_update_equals_stages_and_is_deterministic(lib, ctx, orc, lam):
     assert rel_err(d["eta"], d_s["eta"], 1.0) <= TOL and rel_err(d["ess"], d_s["ess"], 1.0) <= TOL
 
 
+def test_update_writes_pinned_host_output(lib, ctx):
+    """u_apply in pinned host memory (through mppi_device_address): the command lands
+    on the host without a copy, bit for bit the device-memory result, over consecutive
+    updates of a closed loop (warm start carried in u_nom)."""
+    sc = W.c2_line(K=1024, N=40)
+    P = DeviceProblem(lib, sc, t=1)
+    un_d, un_h = P.u_nom.clone(), P.u_nom.clone()
+    ua_d = torch.empty(8, device="cuda")
+    ua_h = torch.full((8,), float("nan"), pin_memory=True)
+    for t in range(3):
+        sol = sc.solve(1 + t)
+        lib.mppi_update(ctx, sc.veh, sc.cost, sol, P.x_hat, P.x_ref, P.obs, P.M, un_d, ua_d)
+        lib.mppi_update(ctx, sc.veh, sc.cost, sol, P.x_hat, P.x_ref, P.obs, P.M, un_h, ua_h)
+        torch.cuda.synchronize()
+        assert torch.equal(ua_h, ua_d.cpu()) and torch.equal(un_h, un_d)
+    assert lib.device_address(ua_h) == lib.device_address(ua_h)       # cached
+    with pytest.raises(lib.MPPIError):                                 # pageable memory
+        lib.device_address(torch.zeros(8))
+
+
 def test_end_to_end_update_when_kappa_small(lib, ctx, orc):
     """Oracle's own costs: with lambda large enough that kappa <= 1e-5 the whole
     update must match at 1e-4."""
