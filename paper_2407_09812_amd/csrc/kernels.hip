@@ -136,12 +136,12 @@ __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
     } else if (wv == 3) {
         for (int ph = 0; ph < nph; ++ph) {
             if (ph >= 3 && ph < nch + 3)
-                pipe_translation_chunk(a, x_ref, oh, obs_lds, phx, phy, phz, x, ph - 3, lane, P);
+                pipe_translation_chunk<L>(a, x_ref, oh, obs_lds, phx, phy, phz, x, ph - 3, lane, P);
             __syncthreads();
         }
     } else {
         for (int ph = 0; ph < nph; ++ph) {
-            if (ph >= kO) pipe_obstacle_chunk<L, U>(a, obs_lds, S, tested, ph - kO, sb, q, P);
+            if (ph >= kO) pipe_obstacle_chunk<L, U>(a, obs_lds, S, tested, ph - kO, sb, q, wv - kO, P);
             __syncthreads();
         }
     }

@@ -415,6 +415,38 @@ __device__ __forceinline__ void wave_range(float v, float& lo, float& hi)
     hi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b), 63));
 }
 
+// Minimum and maximum over each group of G consecutive lanes (G = 8, 16, 32 or 64),
+// returned in every lane of the group: the butterflies within a row stop once they
+// span G lanes; for G = 32 the row broadcast 15 folds rows 0 and 2 into rows 1 and 3,
+// which are read back.  NaN lanes are handled as in wave_range.
+template <int G>
+__device__ __forceinline__ void group_range(float v, float& lo, float& hi)
+{
+    static_assert(G == 8 || G == 16 || G == 32 || G == 64, "group of 8, 16, 32 or 64 lanes");
+    if (G == 64) {
+        wave_range(v, lo, hi);
+        return;
+    }
+    const bool nan = v != v;
+    float a = nan ? INFINITY : v, b = nan ? -INFINITY : v;
+    range_step<0xB1, 0xF>(a, b);                     // quad_perm [1, 0, 3, 2]
+    range_step<0x4E, 0xF>(a, b);                     // quad_perm [2, 3, 0, 1]
+    range_step<0x141, 0xF>(a, b);                    // row_half_mirror: 8 lanes
+    if (G >= 16) range_step<0x140, 0xF>(a, b);       // row_mirror: 16 lanes
+    if (G == 32) {
+        range_step<0x142, 0xA>(a, b);                // row_bcast:15 into rows 1 and 3
+        const bool low = (__lane_id() & 32) == 0;
+        const float a0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a), 31));
+        const float a1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a), 63));
+        const float b0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b), 31));
+        const float b1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b), 63));
+        a = low ? a0 : a1;
+        b = low ? b0 : b1;
+    }
+    lo = a;
+    hi = b;
+}
+
 // Obstacles in LDS, one block per workgroup (see stage_obstacles):
 //   float4 header (x0, 1 / bin width, R_max + slack, culling on)
 //   kObsBins + 1 bin starts (int, padded to 68): first obstacle with x >= x0 + b w
@@ -450,24 +482,31 @@ __host__ __device__ constexpr size_t obstacle_lds_bytes(int M)
 // 2); the indices past the window reach obstacles outside it or the padding, which add
 // exactly zero, so the result is that of testing the window alone, in the same order.
 // The culling window [i0, i1) for the positions px of the wave's lanes (all active),
-// from the block's header h (read once by the caller).  obstacle_bins issues the bin
-// reads and leaves their values in registers (uniform across the wave), so that a
-// caller can do other work before obstacle_window's readfirstlane waits for them.
+// from the block's header h (read once by the caller).  obstacle_bins_of issues the
+// bin reads for a given x-range [lo, hi] of positions and leaves their values in
+// registers, so that a caller can do other work before it uses them; obstacle_bins
+// takes the range of the whole wave.
+__device__ __forceinline__ void obstacle_bins_of(const float4 h, const float4* __restrict__ blk,
+                                                 float lo, float hi, int& v0, int& v1)
+{
+    const int* bins = reinterpret_cast<const int*>(blk + 1);
+    lo -= h.z;
+    hi += h.z;
+    const float b0 = fminf(fmaxf(floorf((lo - h.x) * h.y), 0.0f), (float)kObsBins);
+    const float b1 = fminf(fmaxf(floorf((hi - h.x) * h.y) + 1.0f, 0.0f), (float)kObsBins);
+    v0 = bins[(int)b0];
+    v1 = bins[(int)b1];
+}
+
 __device__ __forceinline__ void obstacle_bins(const float4 h, const float4* __restrict__ blk,
                                               float px, int M, int& v0, int& v1)
 {
-    const int* bins = reinterpret_cast<const int*>(blk + 1);
     v0 = 0;
     v1 = M;
     if (h.w != 0.0f) {
         float lo, hi;
         wave_range(px, lo, hi);
-        lo -= h.z;
-        hi += h.z;
-        const float b0 = fminf(fmaxf(floorf((lo - h.x) * h.y), 0.0f), (float)kObsBins);
-        const float b1 = fminf(fmaxf(floorf((hi - h.x) * h.y) + 1.0f, 0.0f), (float)kObsBins);
-        v0 = bins[(int)b0];
-        v1 = bins[(int)b1];
+        obstacle_bins_of(h, blk, lo, hi, v0, v1);
     }
 }
 

@@ -222,7 +222,7 @@ struct PipeLds {
     float4 w[2][kPipeChunk][5][64];      // stage rates x, y, z, stage thrust F, (omega, cost)
     float4 r[2][kPipeChunk][5][64];      // stage accelerations x, y, z, q, (omega, cost)
     float4 p[2][kPipeChunk][64];         // p_{j+1} relative to p_hat, tracking cost
-    int2 win[2][kPipeChunk];             // culling window of p_{j+1} over the 64 samples
+    int2 win[2][kPipeChunk][8];          // culling window of p_{j+1} per obstacle wave
     float cu_fwd[2][kPipeChunk][64];     // input cost, forwarded to the obstacle role
 };
 
@@ -314,9 +314,10 @@ __device__ __forceinline__ void pipe_attitude_chunk(const RolloutParams& a, Stat
 
 // Translation role: chunk c of sample `lane` (x holds p relative to p_hat, and v):
 // integrates p and v with the hand-over of the attitude role, scores the tracking cost
-// and takes the culling window of the workgroup's 64 positions (it contains the window
-// of every obstacle wave, so their tests give the same terms); hands p, that cost, the
-// input cost and the window on to the obstacle role.
+// and takes the culling window of each obstacle wave's 64 / L samples (lanes of one
+// group of 64 / L here): the window that wave would take itself; hands p, that cost,
+// the input cost and the windows on to the obstacle role.
+template <int L>
 __device__ __forceinline__ void pipe_translation_chunk(const RolloutParams& a,
                                                        const float* __restrict__ x_ref,
                                                        const float4 oh,
@@ -339,25 +340,29 @@ __device__ __forceinline__ void pipe_translation_chunk(const RolloutParams& a,
         rk4_translational(a.mp, x, A);
         x.qw = qv.x; x.qx = qv.y; x.qy = qv.z; x.qz = qv.w;
         x.wx = wv.x; x.wy = wv.y; x.wz = wv.z;
-        int v0, v1;                        // bin reads in flight during the tracking cost
-        obstacle_bins(oh, obs_lds, x.px, a.M, v0, v1);
+        constexpr int G = 64 / L;
+        int v0 = 0, v1 = a.M;              // bin reads in flight during the tracking cost
+        if (oh.w != 0.0f) {
+            float lo, hi;
+            group_range<G>(x.px, lo, hi);
+            obstacle_bins_of(oh, obs_lds, lo, hi, v0, v1);
+        }
         const float* rf = x_ref + (size_t)13 * (j + 1);
         const float tr = tracking_cost(a.cp, x, rf[0] - phx, rf[1] - phy, rf[2] - phz, rf);
-        const int i0 = __builtin_amdgcn_readfirstlane(v0), i1 = __builtin_amdgcn_readfirstlane(v1);
         P.p[c & 1][s][lane] = make_float4(x.px, x.py, x.pz, tr);
         P.cu_fwd[c & 1][s][lane] = wv.w;
-        if (lane == 0) P.win[c & 1][s] = make_int2(i0, i1);
+        if (lane % G == 0) P.win[c & 1][s][lane / G] = make_int2(v0, v1);
     }
 }
 
-// Obstacle role: chunk c for the sample at position sb of the workgroup, lane q of its
-// L lanes: the obstacle term at the handed-over position, and the running cost in the
-// order of rollout_sample, cu + (tracking + obstacle).
+// Obstacle role (obstacle wave ow): chunk c for the sample at position sb of the
+// workgroup, lane q of its L lanes: the obstacle term at the handed-over position, and
+// the running cost in the order of rollout_sample, cu + (tracking + obstacle).
 template <int L, int U>
 __device__ __forceinline__ void pipe_obstacle_chunk(const RolloutParams& a,
                                                     const float4* __restrict__ obs_lds,
                                                     KahanSum& S, int& tested, int c, int sb, int q,
-                                                    const PipeLds& P)
+                                                    int ow, const PipeLds& P)
 {
     float4 h = P.p[c & 1][0][sb];
     float cu = P.cu_fwd[c & 1][0][sb];
@@ -370,7 +375,7 @@ __device__ __forceinline__ void pipe_obstacle_chunk(const RolloutParams& a,
             h = P.p[c & 1][s + 1][sb];
             cu = P.cu_fwd[c & 1][s + 1][sb];
         }
-        const int2 win = P.win[c & 1][s];
+        const int2 win = P.win[c & 1][s][ow];
         const float co = obstacle_tests<L, U>(a.cp, pt.x, pt.y, pt.z, obs_lds,
                                               __builtin_amdgcn_readfirstlane(win.x),
                                               __builtin_amdgcn_readfirstlane(win.y), q, tested);
