@@ -4,9 +4,10 @@
 Default workload: the single-instance configuration (K = 4096 rollouts, N = 100
 steps of 10 ms, 20 spheres, straight-line reference at 12 m/s) run in closed loop:
 every step is one full MPPI update (rollouts, weights, weighted update, apply and
-shift) followed by one noise-free plant step on the device, with the applied control
-copied to the host and the host synchronised per update ("plain": one solve per
-launch sequence).  Inputs (references for every step, obstacles, warm start) are
+shift) whose applied control the device writes into pinned host memory, one
+noise-free plant step on the device queued behind it, and the host waiting (spinning
+on an event) for the control before the next update ("plain": one solve per launch
+sequence).  Inputs (references for every step, obstacles, warm start) are
 resident on the device before the timed region starts.  The same line carries the
 batched leg (256 uneven vehicles per graph replay) and a short served leg (Poisson
 arrivals, each state estimate predicted over the running median latency).
@@ -199,12 +200,13 @@ def run(args):
         lib.mppi_update(ctx, veh_c, cost_c, solves_c[t], xi, refs[t], obs, M, u_nom, u_host, diag,
                         stream=stream)
         done.record(stream)
+        # the simulated plant (one control period with the command held) is queued
+        # behind the update on the device; the controller waits for its command only
+        lib.mppi_predict(ctx, veh_c, sc.dt, sc.period, xi, u_host, x_buf[(t + 1) % 2],
+                         stream=stream)
         while not done.query():
             pass
         t1 = time.perf_counter()
-        # plant: one control period with the applied command held
-        lib.mppi_predict(ctx, veh_c, sc.dt, sc.period, xi, u_host, x_buf[(t + 1) % 2],
-                         stream=stream)
         if record:
             lat.append((t1 - t0) * 1e3)
 
