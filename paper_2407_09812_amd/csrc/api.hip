@@ -235,10 +235,11 @@ hipEvent_t mppi::take_event(mppi_ctx* ctx)
 namespace {
 
 // The full update in two launches on stream s: the rollouts with the weight
-// statistics (reduced by their last workgroup into dg), then the weighted sum into
-// ctx->u_upd whose last workgroup applies and advances as `ap` says; either over the
-// stored delta_u or, with cfg.fused, over the per-wave partial sums.  mark(1) is
-// called between the two launches.
+// statistics (reduced by their last workgroup into dg), then the weighted sum, which
+// applies and advances as `ap` says: over the stored delta_u, one workgroup per step
+// (the rollout launch copies the warm start into ctx->u_upd for it), or, with
+// cfg.fused, over the per-wave partial sums into ctx->u_upd, whose last workgroup
+// applies.  mark(1) is called between the two launches.
 template <typename Mark>
 hipError_t update_core(mppi_ctx* ctx, const RolloutArgs& a, const LaunchConfig& cfg, float lambda,
                        const float* u_in, const ApplyArgs& ap, mppi_diag* dg, hipStream_t s,
@@ -262,11 +263,11 @@ hipError_t update_core(mppi_ctx* ctx, const RolloutArgs& a, const LaunchConfig& 
             e = launch_merge_sum(ctx->part, a.N, ctx->list_idx, ctx->list_s, ctx->list_n, u_in,
                                  ctx->u_upd, dg, ap, ctx->counters + 1, s);
     } else {
+        tail.u_copy = ctx->u_upd;
         e = cfg.pipe ? launch_rollout_pipe(a, cfg, s, &tail) : launch_rollout(a, cfg, s, &tail);
         if (e == hipSuccess) e = mark(1);
         if (e == hipSuccess)
-            e = launch_update_sum(ctx->S, ctx->du, a.K, a.N, ctx->ld, lambda, u_in, ctx->u_upd, dg, ap,
-                                  s);
+            e = launch_update_sum(ctx->S, ctx->du, a.K, a.N, ctx->ld, lambda, ctx->u_upd, dg, ap, s);
     }
     return e;
 }

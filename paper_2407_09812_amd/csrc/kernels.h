@@ -53,6 +53,7 @@ struct UpdateTail {
     int* list_idx = nullptr;           // single pass: contributing waves [W]
     float* list_s = nullptr;           //   and their factors exp(-(rho_w - rho) / lambda)
     int* list_n = nullptr;
+    float* u_copy = nullptr;           // stored form: the first workgroup copies u_nom [4 N] here
 };
 
 // Apply and advance, done by the last workgroup of the weighted-sum launch.
@@ -78,10 +79,11 @@ hipError_t launch_rollout_pipe(const RolloutArgs& a, const LaunchConfig& cfg, hi
 int rollout_waves(int K, const LaunchConfig& c);   // not for pipe shapes
 hipError_t launch_rollout_fused(const RolloutArgs& a, const LaunchConfig& c, const UpdateTail& tail,
                                 hipStream_t stream);
-// The stored form's weighted sum, then the apply and advance (two launches).
+// The stored form's weighted sum with the apply and advance, one launch; u_src is the
+// copy of the warm start the rollout launch made (UpdateTail::u_copy).
 hipError_t launch_update_sum(const float* S, const float* du, int K, int N, int ld, float lambda,
-                             const float* u_in, float* u_upd, const mppi_diag* diag,
-                             const ApplyArgs& ap, hipStream_t stream);
+                             const float* u_src, const mppi_diag* diag, const ApplyArgs& ap,
+                             hipStream_t stream);
 hipError_t launch_merge_sum(const float* part, int N, const int* list_idx, const float* list_s,
                             const int* list_n, const float* u_in, float* u_upd,
                             const mppi_diag* diag, const ApplyArgs& ap, unsigned int* counter,

@@ -3,13 +3,16 @@
 //   rollout_kernel      one sample per L lanes: in-register Philox noise, rate
 //                       controller, RK4 of the 17-value state, tracking and
 //                       obstacle cost (obstacles staged in LDS)        Eqs. (2)-(3)
+//   rollout_pipe_kernel the same rollouts wave-specialised: noise, body rates,
+//                       attitude, translation and obstacle waves per 64 samples,
+//                       handing chunks of steps over through LDS        Sec. III
 //   weights_kernel      one workgroup: wave-shuffle min, compensated
 //                       sum of exp(-(S - rho)/lambda), normalisation   Eq. (4)
 //   weighted_sum_kernel one workgroup per (j, d) row of delta_u [N][4][ld]:
 //                       coalesced float4 GEMV against the weights       Eq. (5)
 //   update_sum_kernel   the full update's weighted sum, weights formed on the fly
-//                       from the costs and the statistics the rollout launch reduced;
-//                       its last workgroup applies and advances
+//                       from the costs and the statistics the rollout launch reduced,
+//                       one workgroup per step, which also applies and advances
 //   rollout_fused_kernel, merge_sum_kernel   the single pass: per-wave partial sums
 //                       with regenerated noise instead of stored delta_u, then their
 //                       rescaled sum (and apply)
@@ -33,6 +36,8 @@ __global__ __launch_bounds__(256) void rollout_kernel(
     UpdateTail tail)
 {
     extern __shared__ float4 obs_lds[];   // obstacle_lds_bytes(M)
+    if (tail.u_copy && blockIdx.x == 0)   // the warm start, for the sum launch that rewrites it
+        for (int i = threadIdx.x; i < 4 * a.N; i += blockDim.x) tail.u_copy[i] = u_nom[i];
     stage_obstacles(obs_lds, obs, a.M, x_hat[0], x_hat[1], x_hat[2], a.cp.margin);
     __syncthreads();
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -85,6 +90,8 @@ __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
     extern __shared__ float4 lds[];       // obstacles, then PipeLds
     float4* obs_lds = lds;
     PipeLds& P = *reinterpret_cast<PipeLds*>(lds + obstacle_lds_float4(a.M));
+    if (tail.u_copy && blockIdx.x == 0)   // the warm start, for the sum launch that rewrites it
+        for (int i = threadIdx.x; i < 4 * a.N; i += blockDim.x) tail.u_copy[i] = u_nom[i];
     const float phx = x_hat[0], phy = x_hat[1], phz = x_hat[2];
     stage_obstacles(obs_lds, obs, a.M, phx, phy, phz, a.cp.margin);
     __syncthreads();
@@ -165,14 +172,15 @@ __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
     }
 }
 
-// Weighted sum of the stored delta_u, one workgroup per row 4 j + d (Eq. (5)).  The
-// apply and advance follow as their own launch: with hundreds of rows, a device-scope
-// fence in every workgroup (for a last-arrival tail) costs more than the launch.
-__global__ __launch_bounds__(kSumThreads) void update_sum_kernel(
+// Weighted sum of the stored delta_u with the apply and advance, one workgroup per
+// step j (Eq. (5); Algorithm 1): it sums the rows of steps j and j + 1 and writes knot
+// j (and, for j = 0, u_apply), so no workgroup waits for another's result.
+__global__ __launch_bounds__(kSumStepThreads) void update_sum_kernel(
     const float* __restrict__ S, const float* __restrict__ du, int K, int ld, float lambda,
-    const float* __restrict__ u_in, float* __restrict__ u_upd, const mppi_diag* __restrict__ diag)
+    const float* __restrict__ u_src, const mppi_diag* __restrict__ diag, ApplyArgs ap)
 {
-    update_sum_row(S, du, K, ld, lambda, u_in, u_upd, diag, blockIdx.x);
+    update_sum_shift_step(S, du, K, ld, lambda, u_src, ap.P, ap.x_hat, ap.u_nom, ap.u_apply, ap.N,
+                          ap.u_init, ap.alpha, diag, blockIdx.x);
 }
 
 // Single pass: the listed waves' partial sums, 64 columns per workgroup; the last
@@ -354,13 +362,11 @@ hipError_t launch_rollout_pipe(const RolloutArgs& a, const LaunchConfig& c, hipS
 }
 
 hipError_t launch_update_sum(const float* S, const float* du, int K, int N, int ld, float lambda,
-                             const float* u_in, float* u_upd, const mppi_diag* diag,
-                             const ApplyArgs& ap, hipStream_t stream)
+                             const float* u_src, const mppi_diag* diag, const ApplyArgs& ap,
+                             hipStream_t stream)
 {
-    hipLaunchKernelGGL(update_sum_kernel, dim3(4 * N), dim3(kSumThreads), 0, stream, S, du, K, ld,
-                       lambda, u_in, u_upd, diag);
-    hipLaunchKernelGGL(apply_shift_kernel, dim3(1), dim3(256), 0, stream, ap.P, ap.x_hat, u_upd,
-                       ap.u_nom, ap.u_apply, ap.N, ap.u_init, ap.alpha, diag);
+    hipLaunchKernelGGL(update_sum_kernel, dim3(N), dim3(kSumStepThreads), 0, stream, S, du, K, ld,
+                       lambda, u_src, diag, ap);
     return hipGetLastError();
 }
 

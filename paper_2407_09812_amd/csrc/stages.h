@@ -868,6 +868,113 @@ __device__ __forceinline__ void update_sum_row(const float* __restrict__ S, cons
     }
 }
 
+// Weighted sums of step j's rows and of step j + 1's (Eq. (5)), then the apply and
+// advance of knot j (Algorithm 1; Sec. IV-B), one workgroup of kSumStepThreads per
+// step: the workgroup holds both steps the interpolated knot needs, so no other
+// workgroup's result is read.  u_src is a copy of the warm start the update started
+// from (the rollout launch makes it), since u_nom is written here: workgroup j writes
+// the knot workgroup j - 1 reads.  Group d of kSumThreads threads sums control d of
+// steps j and j + 1, each row in update_sum_row's order (the same samples per thread,
+// the same reduction tree), so the results equal those of the separate sum and apply
+// launches bit for bit.
+constexpr int kSumStepThreads = 4 * kSumThreads;
+
+__device__ __forceinline__ void update_sum_shift_step(const float* __restrict__ S,
+                                                      const float* __restrict__ du, int K, int ld,
+                                                      float lambda, const float* __restrict__ u_src,
+                                                      const ModelParams& P,
+                                                      const float* __restrict__ x_hat,
+                                                      float* __restrict__ u_nom,
+                                                      float* __restrict__ u_apply, int N,
+                                                      float4 u_init, float alpha,
+                                                      const mppi_diag* __restrict__ diag, int j)
+{
+    constexpr int nw = kSumThreads / 64;              // waves per group
+    __shared__ float sh[8][nw];
+    const int tid = threadIdx.x, d = tid / kSumThreads, gt = tid % kSumThreads;
+    const int nr = j + 1 < N ? 2 : 1;                 // control d of step j (and j + 1)
+    const bool ok = diag->status == MPPI_OK;
+    float acc[2] = {0.0f, 0.0f};
+    float eta = 1.0f;
+    if (ok) {
+        const float rho = diag->rho;
+        eta = diag->eta;
+        const float scale = 1.44269504089f / lambda;
+        auto wt = [&](float s) { return isfinite(s) ? __builtin_amdgcn_exp2f((rho - s) * scale) : 0.0f; };
+        const float* src = du + (size_t)(4 * j + d) * ld;      // row of step j; + 4 ld: step j + 1
+        if ((ld & 3) == 0) {
+            const int K4 = K >> 2;
+            const float4* c4 = reinterpret_cast<const float4*>(S);
+            for (int i = gt; i < K4; i += 4 * kSumThreads) {   // four float4 pairs in flight
+                float4 w[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int idx = i + u * kSumThreads;
+                    const float4 c = idx < K4 ? c4[idx] : make_float4(INFINITY, INFINITY, INFINITY, INFINITY);
+                    w[u] = make_float4(wt(c.x), wt(c.y), wt(c.z), wt(c.w));
+                }
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    if (r >= nr) break;
+                    const float4* s4 = reinterpret_cast<const float4*>(src + (size_t)(4 * r) * ld);
+                    float4 a[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int idx = i + u * kSumThreads;
+                        a[u] = idx < K4 ? s4[idx] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        acc[r] = fmaf(a[u].x, w[u].x, acc[r]);
+                        acc[r] = fmaf(a[u].y, w[u].y, acc[r]);
+                        acc[r] = fmaf(a[u].z, w[u].z, acc[r]);
+                        acc[r] = fmaf(a[u].w, w[u].w, acc[r]);
+                    }
+                }
+            }
+            for (int k = 4 * K4 + gt; k < K; k += kSumThreads) {
+                const float w = wt(S[k]);
+                for (int r = 0; r < nr; ++r) acc[r] = fmaf(src[(size_t)(4 * r) * ld + k], w, acc[r]);
+            }
+        } else {
+            for (int k = gt; k < K; k += kSumThreads) {
+                const float w = wt(S[k]);
+                for (int r = 0; r < nr; ++r) acc[r] = fmaf(src[(size_t)(4 * r) * ld + k], w, acc[r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) acc[r] += __shfl_xor(acc[r], off);
+            if ((gt & 63) == 0) sh[4 * r + d][gt >> 6] = acc[r];
+        }
+        __syncthreads();
+    }
+    if (tid != 0) return;
+    const float init[4] = {u_init.x, u_init.y, u_init.z, u_init.w};
+    float up[8];                                      // u_upd of steps j (0..3) and j + 1 (4..7)
+    for (int r = 0; r < 8; ++r) {
+        if (r >= 4 * nr) {
+            up[r] = init[r - 4];
+            continue;
+        }
+        float t = 0.0f;
+        if (ok)
+            for (int i = 0; i < nw; ++i) t += sh[r][i];
+        up[r] = ok ? u_src[4 * j + r] + t / eta : u_src[4 * j + r];
+    }
+    if (j == 0) {
+        for (int c = 0; c < 4; ++c) u_apply[c] = up[c];
+        feasible_input(P, x_hat, up, u_apply + 4);
+    }
+    if (!ok) return;   // all costs non-finite: keep the warm start as it was
+    // knot j moves to the value at j + alpha of the interpolant (Sec. IV-B); alpha = 1
+    // is the plain shift, copied exactly
+    const bool shift = alpha == 1.0f;
+    const float keep = 1.0f - alpha;
+    for (int c = 0; c < 4; ++c) u_nom[4 * j + c] = shift ? up[4 + c] : fmaf(alpha, up[4 + c], keep * up[c]);
+}
+
 // Single pass, one workgroup of kMergeThreads = 64 columns x 4 waves: u_out[col] =
 // u_in[col] + sum over the listed waves of s_w P_w[col] / eta (binary64), the waves
 // of the list divided among the workgroup's waves.
