@@ -117,6 +117,49 @@ def test_pipe_rollouts_match_oracle(lib, ctx, orc):
     assert e_du <= TOL and e_S[~flips].max() <= TOL and flips.sum() <= 2
 
 
+def pipe_vs_oracle(lib, ctx, orc, sc, lanes, unroll, ks, n_exact=None):
+    lib.mppi_reserve(ctx, sc.K, sc.N, max(sc.M, 1))
+    P = DeviceProblem(lib, sc)
+    du, S = rollout(lib, ctx, P, lanes, unroll, 1)
+    _, du_o, S_o = orc.rollouts_subset(P.o_veh, P.o_cost, P.o_solve, ks, P.o_x_hat, P.o_u_nom,
+                                       P.o_x_ref, P.o_obs, want_states=False)
+    kt = torch.as_tensor(ks, device="cuda")
+    du_g = du.view(P.N, 4, P.K)[:, :, kt].permute(2, 0, 1).double().cpu().numpy()
+    S_g = S[kt].double().cpu().numpy()
+    e_du = rel_err(du_g, du_o, np.asarray(sc.sigma)).max()
+    e_S = rel_err(S_g, S_o, 1.0)
+    flips = np.abs(np.round((S_g - S_o) / sc.cost["obs_collision"])) >= 1
+    return e_du, e_S, flips, S
+
+
+@pytest.mark.parametrize("K,N,M,lanes", [(1, 30, 20, 2), (65, 1, 20, 4), (130, 7, 0, 1),
+                                         (200, 23, 384, 8), (64, 9, 384, 1)])
+def test_pipe_edge_shapes_match_oracle(lib, ctx, orc, K, N, M, lanes):
+    """One sample; one lane in the last workgroup (K = 65); a single step; no
+    obstacles; the largest obstacle list the pipe takes (M = 384, culled): the
+    perturbations and costs match the oracle at 1e-4."""
+    rng = np.random.default_rng(K + N + M)
+    sc = W.c2_line(K=K, N=N)
+    sc.obstacles = (W.spheres_in_box(rng, M, (-2, -3, 0), (8, 3, 5), 0.05, 0.3) if M
+                    else np.zeros((0, 5)))
+    assert sc.M == M
+    ks = np.arange(K) if K <= 130 else np.arange(0, K, 3)
+    for unroll in (1, 4):
+        e_du, e_S, flips, _ = pipe_vs_oracle(lib, ctx, orc, sc, lanes, unroll, ks)
+        print(f"K={K} N={N} M={M} lanes={lanes} unroll={unroll}: du {e_du:.1e} "
+              f"S {e_S[~flips].max(initial=0.0):.1e} collision-boundary {int(flips.sum())}")
+        assert e_du <= TOL and e_S[~flips].max(initial=0.0) <= TOL and flips.sum() <= 2
+
+
+def test_pipe_longest_horizon(lib, ctx, orc):
+    """N = 4096 through the pipe: costs match the oracle within binary32 drift over
+    41 s of flight (1e-2, as for the one-wave kernel's states) and stay finite."""
+    sc = W.c1_plain(K=64, N=4096)
+    e_du, e_S, flips, S = pipe_vs_oracle(lib, ctx, orc, sc, 1, 1, np.array([0, 31, 63]))
+    print(f"N=4096 pipe: du {e_du:.1e} S {e_S.max():.1e}")
+    assert e_du <= TOL and e_S.max() < 1e-2 and torch.isfinite(S).all()
+
+
 def test_pipe_rejects_too_many_obstacles(lib, ctx):
     with pytest.raises(lib.MPPIError) as e:
         lib.mppi_set_config(ctx, 1024, 50, 500, 64, 4, 1, 0, 1)
