@@ -237,7 +237,7 @@ mppi_status mppi_plant_step(mppi_ctx *ctx, void *stream, const mppi_vehicle *veh
  * partial sums of e_k delta_u (the perturbations regenerated from the counter-based
  * noise), and one merge launch rescales the partials by exp(-(rho_w - rho)/lambda);
  * fused = 0 stores delta_u and runs the weights and the GEMV-shaped weighted sum.
- * pipe = 1 (M <= 384; either fused value) runs the rollouts wave-specialised: per 64
+ * pipe = 1 (M <= 1536; either fused value) runs the rollouts wave-specialised: per 64
  * samples one workgroup of 4 + lanes waves -- noise, body rates, attitude, translation
  * and tracking cost, and `lanes` obstacle-cost waves -- handing chunks of steps over
  * through LDS (block is then 64 (4 + lanes) and the field is ignored); the arithmetic

@@ -70,9 +70,10 @@ struct ApplyArgs {
 // Rollouts (with tail: and the full update's weight statistics).
 hipError_t launch_rollout(const RolloutArgs& a, const LaunchConfig& cfg, hipStream_t stream,
                           const UpdateTail* tail = nullptr);
-// Wave-specialised rollouts (stored delta_u) for M <= kPipeMaxM (the LDS of a
-// workgroup holds the obstacles and the hand-over buffers).
-constexpr int kPipeMaxM = 384;
+// Wave-specialised rollouts for M <= kPipeMaxM: the LDS of a workgroup (160 KB on
+// gfx950) holds the obstacles (32 B each, plus padding) and about 100 KB of hand-over
+// buffers (pipe_lds_bytes).
+constexpr int kPipeMaxM = 1536;
 hipError_t launch_rollout_pipe(const RolloutArgs& a, const LaunchConfig& cfg, hipStream_t stream,
                                const UpdateTail* tail = nullptr);
 // Waves of a rollout launch of this shape (one statistics record each).

@@ -81,6 +81,8 @@ __global__ __launch_bounds__(256) void rollout_fused_kernel(
 // waves 4 .. 4 + L - 1 obstacles and the running cost.  Obstacles and hand-over buffers live in LDS; with
 // tail.stat the obstacle waves write the weight statistics (single pass, kFused: and
 // their partial sums, delta_u not stored) and the last workgroup reduces them.
+static_assert(pipe_lds_bytes(kPipeMaxM) <= 160 * 1024, "the pipe's LDS must fit one gfx950 CU");
+
 template <int L, int U, bool kLag, bool kFused>
 __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
     RolloutParams a, const float* __restrict__ x_hat, const float* __restrict__ x_ref,

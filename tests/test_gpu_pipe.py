@@ -133,11 +133,11 @@ def pipe_vs_oracle(lib, ctx, orc, sc, lanes, unroll, ks, n_exact=None):
 
 
 @pytest.mark.parametrize("K,N,M,lanes", [(1, 30, 20, 2), (65, 1, 20, 4), (130, 7, 0, 1),
-                                         (200, 23, 384, 8), (64, 9, 384, 1)])
+                                         (200, 23, 384, 8), (64, 9, 384, 1), (70, 6, 1536, 8)])
 def test_pipe_edge_shapes_match_oracle(lib, ctx, orc, K, N, M, lanes):
     """One sample; one lane in the last workgroup (K = 65); a single step; no
-    obstacles; the largest obstacle list the pipe takes (M = 384, culled): the
-    perturbations and costs match the oracle at 1e-4."""
+    obstacles; culled lists (M = 384) and the largest list the pipe takes (M = 1536,
+    uncut, 150 KB of LDS): the perturbations and costs match the oracle at 1e-4."""
     rng = np.random.default_rng(K + N + M)
     sc = W.c2_line(K=K, N=N)
     sc.obstacles = (W.spheres_in_box(rng, M, (-2, -3, 0), (8, 3, 5), 0.05, 0.3) if M
@@ -162,5 +162,5 @@ def test_pipe_longest_horizon(lib, ctx, orc):
 
 def test_pipe_rejects_too_many_obstacles(lib, ctx):
     with pytest.raises(lib.MPPIError) as e:
-        lib.mppi_set_config(ctx, 1024, 50, 500, 64, 4, 1, 0, 1)
+        lib.mppi_set_config(ctx, 1024, 50, 1537, 64, 4, 1, 0, 1)
     assert e.value.status == -1
