@@ -61,7 +61,7 @@ SCENES = [("c2", lambda: W.c2_line(K=700, N=61)), ("c3", lambda: W.c3_agile(K=20
 
 
 @pytest.mark.parametrize("scene", [s[0] for s in SCENES])
-def test_pipe_equals_one_wave_kernel_bitwise(lib, ctx, scene):
+def test_pipe_matches_one_wave_kernel(lib, ctx, scene):
     sc = dict(SCENES)[scene]()
     P = DeviceProblem(lib, sc, t=2)
     for lanes in (1, 2, 4, 8):
