@@ -310,7 +310,8 @@ mppi_status mppi_batch_reserve(mppi_ctx *ctx, const mppi_request *reqs, int32_t 
 
 /* MPPI updates of n independent instances with uneven K, N and M in one launch
  * sequence on `stream` (Algorithm 1 loop body for each; the same results, bit for
- * bit, as mppi_update with the same lanes per sample, see mppi_diag.lanes).  A persistent rollout kernel
+ * bit, as mppi_update with the same lanes per sample, stored form, pipe = 0, see
+ * mppi_diag.lanes).  A persistent rollout kernel
  * takes (instance, sample tile) items longest first from a device queue; weights,
  * weighted sums and shifts follow per instance.  With use_graph the sequence is a HIP
  * graph captured once per launch shape and replayed.  Host-side planning is copied
@@ -417,8 +418,7 @@ mppi_status mppi_server_restore(mppi_server *srv, const void *host_buf, size_t s
 
 /* Device time of mppi_update's two launches -- rollout_ms: the rollouts with the
  * weight statistics their last workgroup reduces; sum_ms: the weighted sum (stored
- * delta_u or single-pass partial sums) with the apply and advance of its last
- * workgroup -- and of mppi_batch_update's rollout stage and remaining stages, measured
+ * delta_u or single-pass partial sums) with the apply and advance -- and of mppi_batch_update's rollout stage and remaining stages, measured
  * with HIP events on the call's stream while enabled.  While profiling, batches are
  * launched kernel by kernel (no graph replay) so that the events can bracket the
  * rollout stage. */

@@ -561,10 +561,11 @@ __device__ __forceinline__ void feasible_input(const ModelParams& P, const float
 // The update in two launches.  The rollout launch ends with per-wave statistics of
 // the weights (Eq. (4) relative to each wave's minimum), which its last workgroup
 // reduces into the update's rho, eta and diagnostics; the second launch forms the
-// weighted sum (Eq. (5)) and its last workgroup applies and advances the warm start.
-// The weighted sum reads either the stored delta_u (a GEMV) or, in the single pass,
-// per-wave partial sums that the rollout waves formed from regenerated noise, so that
-// delta_u never goes to memory.
+// weighted sum (Eq. (5)) and applies and advances the warm start.  The weighted sum
+// reads either the stored delta_u (a GEMV, one workgroup per step, which also writes
+// that step's knot) or, in the single pass, per-wave partial sums that the rollout
+// waves formed from regenerated noise, so that delta_u never goes to memory (its last
+// workgroup applies).
 // ---------------------------------------------------------------------------
 
 // Eq. (4) over one wave, relative to its own minimum.
