@@ -254,8 +254,10 @@ typedef struct mppi_launch_config {
 } mppi_launch_config;
 
 /* The shape mppi_update / mppi_rollout use for (K, N, M): a stored entry for the
- * size class (powers of two of K, N and M), else a heuristic that aims at one wave
- * per SIMD.  Host-only. */
+ * size class (powers of two of K, N and M), else a heuristic: the wave-specialised
+ * rollouts (pipe = 1, stored form) with 1, 2, 4 or 8 lanes for M < 16, < 64, < 128 or
+ * more, and beyond the pipe's obstacle limit the one-wave kernel aiming at one wave per
+ * SIMD.  Host-only. */
 mppi_status mppi_get_config(const mppi_ctx *ctx, int32_t K, int32_t N, int32_t M,
                             mppi_launch_config *out);
 /* Store a shape for the size class of (K, N, M).  MPPI_E_INVALID_ARG for a shape
@@ -335,8 +337,10 @@ mppi_status mppi_batch_set_config(mppi_ctx *ctx, const mppi_batch_config *cfg);
  * requests whenever one of n_streams slots is free and the request fits that slot's
  * share of budget_bytes (its delta_u, costs, weights and inputs), one request per
  * vehicle in flight (the next update starts from the previous result), in arrival
- * order, and launches them as one batch (mppi_batch_update) on the slot's stream;
- * batches on different slots overlap on the device.  A request with horizon N uses
+ * order, and launches them as one batch (mppi_batch_update) on the slot's stream --
+ * a lone request as mppi_update, whose default shape runs the wave-specialised
+ * rollouts (each slot reserves one K_max x N_max x M_max instance for it, beyond
+ * budget_bytes); batches on different slots overlap on the device.  A request with horizon N uses
  * the first N rows of its vehicle's warm start and advances them.  With a delay, the
  * request's state estimate is first moved forward by mppi_predict's model steps with
  * the vehicle's last served command held (u_init before its first request); each
@@ -380,7 +384,8 @@ typedef struct mppi_server_result {
     double submit_s, launch_s, done_s;   /* server clock, seconds since creation    */
     int32_t K, N;
     float delay;                   /* delay the state estimate was predicted over  */
-    int32_t reserved;
+    int32_t pipe;                  /* 1: run alone by mppi_update with pipe = 1;
+                                      0: by mppi_batch_update or the one-wave kernel */
 } mppi_server_result;
 
 typedef struct mppi_server_stats {

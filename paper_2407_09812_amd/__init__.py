@@ -100,7 +100,7 @@ class ServerResult(C.Structure):
     _fields_ = [("ticket", C.c_uint64), ("vehicle_id", C.c_uint32), ("t", C.c_uint32),
                 ("u_apply", C.c_float * 8), ("diag", Diag), ("submit_s", C.c_double),
                 ("launch_s", C.c_double), ("done_s", C.c_double), ("K", C.c_int32),
-                ("N", C.c_int32), ("delay", C.c_float), ("reserved", C.c_int32)]
+                ("N", C.c_int32), ("delay", C.c_float), ("pipe", C.c_int32)]
 
 
 class ServerStats(C.Structure):
@@ -478,7 +478,7 @@ def _result_dict(r: ServerResult) -> dict:
                 status=r.diag.status, rho=r.diag.rho, ess=r.diag.ess, argmin=r.diag.argmin,
                 lanes=r.diag.lanes,
                 submit_s=r.submit_s, launch_s=r.launch_s, done_s=r.done_s, K=r.K, N=r.N,
-                delay=r.delay, latency_s=r.done_s - r.submit_s)
+                delay=r.delay, pipe=r.pipe, latency_s=r.done_s - r.submit_s)
 
 
 class Server:

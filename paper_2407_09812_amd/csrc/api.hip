@@ -200,12 +200,23 @@ std::tuple<int, int, int> size_class(int K, int N, int M)
 
 // One wave per SIMD (1024 on the chip) is the target for a lone instance; lanes
 // beyond one per sample only pay off when there are obstacles to divide.
+// Without a tuned entry: the wave-specialised rollouts (the fastest form for every
+// single instance measured, see the autotuner's choices), with more obstacle lanes for
+// longer obstacle lists; past their obstacle limit the one-wave kernel, aiming at one
+// wave per SIMD.
 LaunchConfig heuristic_config(int K, int M)
 {
+    LaunchConfig c;
+    if (M <= kPipeMaxM) {
+        c.block = 64;
+        c.lanes = M < 16 ? 1 : M < 64 ? 2 : M < 128 ? 4 : 8;
+        c.unroll = 1;
+        c.pipe = 1;
+        return c;
+    }
     const int waves = (K + 63) / 64;
     int lanes = 1;
     while (lanes < 8 && waves * lanes * 2 <= 1024 && M >= 8 * lanes) lanes *= 2;
-    LaunchConfig c;
     c.lanes = lanes;
     c.block = (waves * lanes >= 1024) ? 256 : 64;
     c.unroll = M >= 16 ? 4 : 1;

@@ -113,6 +113,7 @@ struct Slot {
     std::vector<uint32_t> ts;
     std::vector<float> delays;
     std::vector<mppi_request> reqs;
+    int32_t pipe = 0;          // the batch is one request run by mppi_update's pipe
     double launch_s = 0.0;
 };
 
@@ -194,6 +195,7 @@ void harvest(mppi_server* s, Slot& sl)
         r.K = p.K;
         r.N = p.N;
         r.delay = sl.delays[i];
+        r.pipe = sl.pipe;
         s->results[p.ticket] = r;
         if (s->latency.size() < kLatencyWindow) {
             s->latency.push_back(now - p.submit_s);
@@ -315,8 +317,21 @@ bool dispatch(mppi_server* s, Slot& sl)
         hipLaunchKernelGGL(serve_predict_kernel, dim3(grid), dim3(64), 0, sl.stream, items_dev, n);
         e = hipGetLastError();
     }
-    mppi_status st = e == hipSuccess ? mppi_batch_update(sl.ctx, sl.stream, sl.reqs.data(), n)
-                                     : MPPI_E_HIP;
+    // A lone request runs as a single-instance update (wave-specialised rollouts under
+    // the default shape), a batch as one batched launch sequence.
+    mppi_status st = MPPI_E_HIP;
+    sl.pipe = 0;
+    if (e == hipSuccess && n == 1) {
+        const mppi_request& r = sl.reqs[0];
+        mppi_launch_config cfg{};
+        st = mppi_get_config(sl.ctx, r.solve.K, r.solve.N, r.M, &cfg);
+        if (st == MPPI_OK)
+            st = mppi_update(sl.ctx, sl.stream, &r.veh, &r.cost, &r.solve, r.x_hat, r.x_ref, r.obs, r.M,
+                             r.u_nom, r.u_apply, r.diag);
+        sl.pipe = cfg.pipe != 0 && r.M <= kPipeMaxM ? 1 : 0;
+    } else if (e == hipSuccess) {
+        st = mppi_batch_update(sl.ctx, sl.stream, sl.reqs.data(), n);
+    }
     if (st == MPPI_OK) {
         hipLaunchKernelGGL(serve_record_kernel, dim3(grid), dim3(64), 0, sl.stream, items_dev, n);
         e = hipGetLastError();
@@ -443,6 +458,7 @@ mppi_status mppi_server_create(const mppi_server_cfg* cfg, mppi_server** out)
         ok = mppi_create(cfg->device, &sl.ctx) == MPPI_OK &&
              batch_reserve_raw(sl.ctx, mb, cap.du, cap.k, cap.u, cap.items, std::max(cfg->M_max, 1)) ==
                  MPPI_OK &&
+             mppi_reserve(sl.ctx, cfg->K_max, cfg->N_max, cfg->M_max) == MPPI_OK &&
              hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
              hipMalloc(&sl.in_dev, cap.in_bytes) == hipSuccess &&
