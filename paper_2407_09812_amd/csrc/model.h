@@ -460,6 +460,7 @@ constexpr int kObsBins = 64;
 constexpr int kObsHeaderFloat4 = 1 + 68 / 4;        // header + padded bin table
 constexpr int kObsPad = 64;                         // >= 2 L max(U, 2) - 1, L <= 8, U <= 4
 constexpr int kCullMin = 16, kCullMax = 512;       // sorted and culled for M in this range
+constexpr int kCullKeysInLds = 64;                 // from this M the sort ranks keys in LDS
 constexpr float kCullSlack = 1.0e-3f;              // m, covers rounding of the x tests
 
 // float4 slots of the obstacle block (header, bins, obstacles, padding).

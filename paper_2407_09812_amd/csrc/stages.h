@@ -32,24 +32,62 @@ __device__ __forceinline__ void stage_obstacles(float4* blk, const mppi_obstacle
     float4* o_lds = blk + kObsHeaderFloat4;
     int* bins = reinterpret_cast<int*>(blk + 1);
     const bool cull = M >= kCullMin && M <= kCullMax;
-    if (threadIdx.x == 0) s_rmax = 0u;
-    __syncthreads();
-    for (int i = threadIdx.x; i < M; i += blockDim.x) {
+    auto put = [&](int i, int rank) {
         const mppi_obstacle o = obs[i];
-        const float key = o.c[0] - phx;
-        int rank = i;
-        if (cull) {
-            rank = 0;
-            for (int j = 0; j < M; ++j) {
-                const float kj = obs[j].c[0] - phx;
-                rank += (kj < key || (kj == key && j < i)) ? 1 : 0;
-            }
-        }
         const float R = o.r + margin;
-        o_lds[2 * rank] = make_float4(key, o.c[1] - phy, o.c[2] - phz,
+        o_lds[2 * rank] = make_float4(o.c[0] - phx, o.c[1] - phy, o.c[2] - phz,
                                       o.type == MPPI_VCYLINDER ? 0.0f : 1.0f);
         o_lds[2 * rank + 1] = make_float4(o.r * o.r, R * R, R, 0.0f);
         atomicMax(&s_rmax, __float_as_uint(fmaxf(R, 0.0f)));
+    };
+    if (threadIdx.x == 0) s_rmax = 0u;
+    if (cull && M >= kCullKeysInLds) {
+        // long lists: the sort keys (x relative to p_hat) go to LDS first, where the
+        // obstacles land afterwards, padded to whole float4 with +inf, and each rank
+        // reads them four at a time (a global load per obstacle costs more)
+        float* keys = reinterpret_cast<float*>(o_lds);
+        const int M4 = (M + 3) >> 2;
+        for (int j = threadIdx.x; j < 4 * M4; j += blockDim.x)
+            keys[j] = j < M ? obs[j].c[0] - phx : INFINITY;
+        __syncthreads();
+        int ranks[kCullMax / 64];                       // blockDim >= 64
+#pragma unroll
+        for (int n = 0; n < kCullMax / 64; ++n) {
+            const int i = threadIdx.x + n * blockDim.x;
+            ranks[n] = 0;
+            if (i < M) {
+                const float key = keys[i];
+                const float4* k4 = reinterpret_cast<const float4*>(keys);
+                for (int m = 0; m < M4; ++m) {
+                    const float4 kv = k4[m];
+                    const int jj = 4 * m;
+                    ranks[n] += (kv.x < key || (kv.x == key && jj < i)) ? 1 : 0;
+                    ranks[n] += (kv.y < key || (kv.y == key && jj + 1 < i)) ? 1 : 0;
+                    ranks[n] += (kv.z < key || (kv.z == key && jj + 2 < i)) ? 1 : 0;
+                    ranks[n] += (kv.w < key || (kv.w == key && jj + 3 < i)) ? 1 : 0;
+                }
+            }
+        }
+        __syncthreads();                                // keys read; the obstacles land
+#pragma unroll
+        for (int n = 0; n < kCullMax / 64; ++n) {
+            const int i = threadIdx.x + n * blockDim.x;
+            if (i < M) put(i, ranks[n]);
+        }
+    } else {
+        __syncthreads();                                // s_rmax set
+        for (int i = threadIdx.x; i < M; i += blockDim.x) {
+            int rank = i;
+            if (cull) {                                 // short lists: keys from global
+                const float key = obs[i].c[0] - phx;
+                rank = 0;
+                for (int j = 0; j < M; ++j) {
+                    const float kj = obs[j].c[0] - phx;
+                    rank += (kj < key || (kj == key && j < i)) ? 1 : 0;
+                }
+            }
+            put(i, rank);
+        }
     }
     for (int i = threadIdx.x; i < kObsPad; i += blockDim.x) {
         const int m = (M > 0 ? M : 0) + i;
