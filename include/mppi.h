@@ -421,9 +421,11 @@ mppi_status mppi_server_restore(mppi_server *srv, const void *host_buf, size_t s
 
 /* --- profiling ---------------------------------------------------------------- */
 
-/* Device time of mppi_update's two launches -- rollout_ms: the rollouts with the
- * weight statistics their last workgroup reduces; sum_ms: the weighted sum (stored
- * delta_u or single-pass partial sums) with the apply and advance -- and of mppi_batch_update's rollout stage and remaining stages, measured
+/* Device time of mppi_update's two launches -- rollout_ms: the rollouts with each
+ * wave's weight statistics (reduced by the single pass's last workgroup); sum_ms: the
+ * weighted sum (stored delta_u, whose workgroups reduce the statistics first, or the
+ * single-pass partial sums) with the apply and advance -- and of mppi_batch_update's
+ * rollout stage and remaining stages, measured
  * with HIP events on the call's stream while enabled.  While profiling, batches are
  * launched kernel by kernel (no graph replay) so that the events can bracket the
  * rollout stage. */

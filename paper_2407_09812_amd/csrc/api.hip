@@ -278,7 +278,9 @@ hipError_t update_core(mppi_ctx* ctx, const RolloutArgs& a, const LaunchConfig& 
         e = cfg.pipe ? launch_rollout_pipe(a, cfg, s, &tail) : launch_rollout(a, cfg, s, &tail);
         if (e == hipSuccess) e = mark(1);
         if (e == hipSuccess)
-            e = launch_update_sum(ctx->S, ctx->du, a.K, a.N, ctx->ld, lambda, ctx->u_upd, dg, ap, s);
+            e = launch_update_sum(ctx->S, ctx->du, a.K, a.N, ctx->ld, lambda, ctx->u_upd, ctx->wstat,
+                                  cfg.pipe ? (a.K + 63) / 64 * cfg.lanes : rollout_waves(a.K, cfg),
+                                  cfg.lanes, dg, ap, s);
     }
     return e;
 }

@@ -6,7 +6,7 @@
 //                          items, longest first, from a device queue, stages that
 //                          instance's obstacles in LDS, rolls the tile out and writes
 //                          its waves' weight statistics
-//   batch_stats_kernel     one wave per instance reduces its weight statistics
+//   batch_stats_kernel     eight waves per instance reduce its weight statistics
 //   batch_wsum_kernel      persistent over all instances' delta_u rows
 //   batch_apply_kernel     one workgroup per instance applies and advances
 // Every stage calls the same device bodies as the one-instance kernels, so an
@@ -71,13 +71,14 @@ __global__ __launch_bounds__(256) void batch_rollout_kernel(BatchHeader* hdr,
     }
 }
 
-__global__ __launch_bounds__(64) void batch_stats_kernel(const BatchHeader* __restrict__ hdr,
+__global__ __launch_bounds__(64 * kStatParts) void batch_stats_kernel(const BatchHeader* __restrict__ hdr,
                                                         const InstanceDesc* __restrict__ descs)
 {
     const int i = blockIdx.x;
     if (i >= hdr->n_inst) return;
     const InstanceDesc& D = descs[i];
-    reduce_wave_stats(D.stat, D.W, D.lambda, D.lanes, D.diag, nullptr, nullptr, nullptr);
+    const StatSums t = reduce_stat_parts<8>(D.stat, D.W, D.lambda);
+    if (threadIdx.x == 0) write_stat_diag(t, D.lanes, D.diag);
 }
 
 __global__ __launch_bounds__(kSumThreads) void batch_wsum_kernel(const BatchHeader* __restrict__ hdr,
@@ -145,7 +146,8 @@ hipError_t launch_batch(BatchHeader* hdr, const InstanceDesc* descs, const WorkI
 hipError_t launch_batch_tail(BatchHeader* hdr, const InstanceDesc* descs, int n_cap, int cu_count,
                              hipStream_t stream)
 {
-    hipLaunchKernelGGL(batch_stats_kernel, dim3(n_cap), dim3(64), 0, stream, hdr, descs);
+    hipLaunchKernelGGL(batch_stats_kernel, dim3(n_cap), dim3(64 * kStatParts), 0, stream, hdr,
+                       descs);
     hipLaunchKernelGGL(batch_wsum_kernel, dim3(cu_count * 8), dim3(kSumThreads), 0, stream, hdr,
                        descs);
     hipLaunchKernelGGL(batch_apply_kernel, dim3(n_cap), dim3(256), 0, stream, hdr, descs);

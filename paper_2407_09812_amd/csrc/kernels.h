@@ -83,8 +83,8 @@ hipError_t launch_rollout_fused(const RolloutArgs& a, const LaunchConfig& c, con
 // The stored form's weighted sum with the apply and advance, one launch; u_src is the
 // copy of the warm start the rollout launch made (UpdateTail::u_copy).
 hipError_t launch_update_sum(const float* S, const float* du, int K, int N, int ld, float lambda,
-                             const float* u_src, const mppi_diag* diag, const ApplyArgs& ap,
-                             hipStream_t stream);
+                             const float* u_src, const WaveStat* stat, int W, int lanes,
+                             mppi_diag* diag, const ApplyArgs& ap, hipStream_t stream);
 hipError_t launch_merge_sum(const float* part, int N, const int* list_idx, const float* list_s,
                             const int* list_n, const float* u_in, float* u_upd,
                             const mppi_diag* diag, const ApplyArgs& ap, unsigned int* counter,

@@ -10,9 +10,9 @@
 //                       sum of exp(-(S - rho)/lambda), normalisation   Eq. (4)
 //   weighted_sum_kernel one workgroup per (j, d) row of delta_u [N][4][ld]:
 //                       coalesced float4 GEMV against the weights       Eq. (5)
-//   update_sum_kernel   the full update's weighted sum, weights formed on the fly
-//                       from the costs and the statistics the rollout launch reduced,
-//                       one workgroup per step, which also applies and advances
+//   update_sum_kernel   the full update's weighted sum, one workgroup per step: it
+//                       reduces the rollout waves' weight statistics, forms the
+//                       weights on the fly from the costs, applies and advances
 //   rollout_fused_kernel, merge_sum_kernel   the single pass: per-wave partial sums
 //                       with regenerated noise instead of stored delta_u, then their
 //                       rescaled sum (and apply)
@@ -27,7 +27,7 @@
 namespace mppi {
 
 // Rollouts; with stat (a full update), each wave also writes its weight statistics
-// and the last workgroup reduces them into diag.
+// (the sum launch reduces them).
 template <int L, int U, bool kLag, bool kDump>
 __global__ __launch_bounds__(256) void rollout_kernel(
     RolloutParams a, const float* __restrict__ x_hat, const float* __restrict__ x_ref,
@@ -46,9 +46,6 @@ __global__ __launch_bounds__(256) void rollout_kernel(
                                                       obs_lds, k, q);
     if (tail.stat == nullptr) return;                       // launch-uniform
     write_wave_stat(tail.stat + (g >> 6), wave_sums(S, k, q, k < a.K, tail.lambda), false);
-    if (last_to_arrive(tail.counter))
-        reduce_wave_stats(tail.stat, (int)(gridDim.x * blockDim.x >> 6), tail.lambda, L, tail.diag,
-                          nullptr, nullptr, nullptr);
 }
 
 // Single pass: rollouts, per-wave statistics and partial sums; the last workgroup
@@ -79,8 +76,9 @@ __global__ __launch_bounds__(256) void rollout_fused_kernel(
 // Wave-specialised rollouts of 64 samples per workgroup (roles in stages.h): wave 0
 // noise, wave 1 body rates, wave 2 attitude, wave 3 translation and tracking cost,
 // waves 4 .. 4 + L - 1 obstacles and the running cost.  Obstacles and hand-over buffers live in LDS; with
-// tail.stat the obstacle waves write the weight statistics (single pass, kFused: and
-// their partial sums, delta_u not stored) and the last workgroup reduces them.
+// tail.stat the obstacle waves write the weight statistics, which the sum launch
+// reduces (single pass, kFused: and their partial sums, delta_u not stored, and the
+// last workgroup reduces the statistics with the list of contributing waves).
 static_assert(pipe_lds_bytes(kPipeMaxM) <= 160 * 1024, "the pipe's LDS must fit one gfx950 CU");
 
 template <int L, int U, bool kLag, bool kFused>
@@ -167,10 +165,10 @@ __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
         else if (tail.stat)
             write_wave_stat(tail.stat + w, wave_sums(S.s, k, q, valid, tail.lambda), false);
     }
-    if (tail.stat && last_to_arrive(tail.counter)) {
-        reduce_wave_stats(tail.stat, (int)gridDim.x * L, tail.lambda, L, tail.diag,
-                          kFused ? tail.list_idx : nullptr, tail.list_s, tail.list_n);
-        if (kFused && threadIdx.x == 0) *tail.rho_run = 0x7f800000u;   // every wave has published
+    if (kFused && last_to_arrive(tail.counter)) {
+        reduce_wave_stats(tail.stat, (int)gridDim.x * L, tail.lambda, L, tail.diag, tail.list_idx,
+                          tail.list_s, tail.list_n);
+        if (threadIdx.x == 0) *tail.rho_run = 0x7f800000u;   // every wave has published
     }
 }
 
@@ -179,10 +177,11 @@ __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
 // j (and, for j = 0, u_apply), so no workgroup waits for another's result.
 __global__ __launch_bounds__(kSumStepThreads) void update_sum_kernel(
     const float* __restrict__ S, const float* __restrict__ du, int K, int ld, float lambda,
-    const float* __restrict__ u_src, const mppi_diag* __restrict__ diag, ApplyArgs ap)
+    const float* __restrict__ u_src, const WaveStat* __restrict__ stat, int W, int lanes,
+    mppi_diag* __restrict__ diag, ApplyArgs ap)
 {
     update_sum_shift_step(S, du, K, ld, lambda, u_src, ap.P, ap.x_hat, ap.u_nom, ap.u_apply, ap.N,
-                          ap.u_init, ap.alpha, diag, blockIdx.x);
+                          ap.u_init, ap.alpha, stat, W, lanes, diag, blockIdx.x);
 }
 
 // Single pass: the listed waves' partial sums, 64 columns per workgroup; the last
@@ -364,11 +363,11 @@ hipError_t launch_rollout_pipe(const RolloutArgs& a, const LaunchConfig& c, hipS
 }
 
 hipError_t launch_update_sum(const float* S, const float* du, int K, int N, int ld, float lambda,
-                             const float* u_src, const mppi_diag* diag, const ApplyArgs& ap,
-                             hipStream_t stream)
+                             const float* u_src, const WaveStat* stat, int W, int lanes,
+                             mppi_diag* diag, const ApplyArgs& ap, hipStream_t stream)
 {
     hipLaunchKernelGGL(update_sum_kernel, dim3(N), dim3(kSumStepThreads), 0, stream, S, du, K, ld,
-                       lambda, u_src, diag, ap);
+                       lambda, u_src, stat, W, lanes, diag, ap);
     return hipGetLastError();
 }
 

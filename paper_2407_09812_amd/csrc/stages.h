@@ -764,14 +764,125 @@ __device__ __forceinline__ bool last_to_arrive(unsigned int* counter)
     return last_of(counter, gridDim.x * gridDim.y * gridDim.z, true);
 }
 
-// Reduce the per-wave statistics stat[0..W) of one update: rho = min rho_w with its
-// first sample, n_finite, and with s_w = exp(-(rho_w - rho) / lambda), eta = sum_w s_w
-// eta_w and sum w_k^2 = sum_w s_w^2 q_w / eta^2 (binary64 sums), written to diag
-// (Eq. (4); ess = 1 / sum w_k^2).  With list_idx, also the waves with s_w > 0 that
-// formed partial sums, in index order, with their s_w (single pass).  Done by the
-// first wave of the calling workgroup in a fixed order (lane l takes l, l + 64, ...),
-// so the result does not depend on the workgroup size; eight records are loaded at a
-// time per lane.
+// Records of wave statistics are split into kStatParts fixed parts: part p holds records
+// 64 (p + kStatParts i) + l for lane l, i = 0, 1, ...  A lane sums its records in i order,
+// a part's lanes are combined by one fixed shuffle tree and the parts in p order, so the
+// binary64 sums depend on W alone: not on how many waves of the calling workgroup share
+// the parts (wave v takes parts v, v + waves, ...) nor on how many records a lane has in
+// flight (kB).
+constexpr int kStatParts = 8;
+constexpr int kStatStride = 64 * kStatParts;   // records between a lane's consecutive ones
+
+template <int kB>
+__device__ __forceinline__ void load_stat_batch(const WaveStat* __restrict__ stat, int W, int w0,
+                                                WaveStat (&r)[kB])
+{
+#pragma unroll
+    for (int u = 0; u < kB; ++u)             // unconditional loads: one wait for the batch
+        r[u] = stat[w0 + kStatStride * u < W ? w0 + kStatStride * u : W - 1];
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+        if (w0 + kStatStride * u >= W) r[u].n = 0;
+}
+
+struct StatSums {
+    float rho;          // minimum finite cost (+inf if none)
+    int argmin, nf;     // its first sample, finite costs
+    double eta, q2;     // sum_w s_w eta_w, sum_w s_w^2 q_w
+};
+
+// The per-wave statistics stat[0..W) of one update reduced, returned to every thread of
+// the calling workgroup (which it synchronises): rho = min rho_w with its first sample,
+// n_finite, and with s_w = exp(-(rho_w - rho) / lambda), eta = sum_w s_w eta_w and
+// sum_w s_w^2 q_w (binary64, in the fixed part order above; Eq. (4)).  When every part
+// is one batch held by a wave of its own, the records stay in registers between the
+// minimum pass and the sum pass: one memory round trip in all.
+template <int kB>
+__device__ inline StatSums reduce_stat_parts(const WaveStat* __restrict__ stat, int W, float lambda)
+{
+    __shared__ float sh_v[kStatParts];
+    __shared__ int sh_i[kStatParts], sh_n[kStatParts];
+    __shared__ double sh_eta[kStatParts], sh_q[kStatParts];
+    const int nw = (int)(blockDim.x >> 6);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const float scale = 1.44269504089f / lambda;
+    const int used = (W + 63) / 64 < kStatParts ? (W + 63) / 64 : kStatParts;   // parts with records
+    const bool keep = W <= kStatStride * kB && used <= nw;
+    WaveStat r[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) r[u] = WaveStat{INFINITY, 0.0f, 0.0f, 0.0f, -1, 0, 0, 0};
+
+    for (int p = wv; p < kStatParts; p += nw) {
+        float mv = INFINITY;
+        int mi = INT_MAX, nf = 0;
+        for (int w0 = 64 * p + lane; w0 < W; w0 += kStatStride * kB) {
+            load_stat_batch<kB>(stat, W, w0, r);
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                nf += r[u].n;
+                if (r[u].n > 0) argmin_merge(mv, mi, r[u].rho, r[u].argmin);
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const float v2 = __shfl_xor(mv, off);
+            const int i2 = __shfl_xor(mi, off);
+            argmin_merge(mv, mi, v2, i2);
+            nf += __shfl_xor(nf, off);
+        }
+        if (lane == 0) { sh_v[p] = mv; sh_i[p] = mi; sh_n[p] = nf; }
+    }
+    __syncthreads();
+    StatSums t;
+    t.rho = sh_v[0]; t.argmin = sh_i[0]; t.nf = sh_n[0];
+#pragma unroll
+    for (int p = 1; p < kStatParts; ++p) { argmin_merge(t.rho, t.argmin, sh_v[p], sh_i[p]); t.nf += sh_n[p]; }
+    t.eta = 0.0; t.q2 = 0.0;
+    if (t.nf == 0) return t;                   // uniform: every thread read the same parts
+
+    for (int p = wv; p < kStatParts; p += nw) {
+        double eta = 0.0, q2 = 0.0;
+        for (int w0 = 64 * p + lane; w0 < W; w0 += kStatStride * kB) {
+            if (!keep) load_stat_batch<kB>(stat, W, w0, r);
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                if (r[u].n > 0) {
+                    const double f = (double)__builtin_amdgcn_exp2f((t.rho - r[u].rho) * scale);
+                    eta += f * ((double)r[u].eta_s + (double)r[u].eta_c);
+                    q2 += f * f * (double)r[u].q;
+                }
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            eta += __shfl_xor(eta, off);
+            q2 += __shfl_xor(q2, off);
+        }
+        if (lane == 0) { sh_eta[p] = eta; sh_q[p] = q2; }
+    }
+    __syncthreads();
+    t.eta = sh_eta[0]; t.q2 = sh_q[0];
+#pragma unroll
+    for (int p = 1; p < kStatParts; ++p) { t.eta += sh_eta[p]; t.q2 += sh_q[p]; }
+    return t;
+}
+
+// diag from the reduced statistics (ess = 1 / sum w_k^2 = eta^2 / sum_w s_w^2 q_w).
+__device__ __forceinline__ void write_stat_diag(const StatSums& t, int lanes, mppi_diag* __restrict__ diag)
+{
+    diag->rho = t.rho; diag->argmin = t.nf > 0 ? t.argmin : -1; diag->n_finite = t.nf; diag->lanes = lanes;
+    if (t.nf == 0) {
+        diag->eta = 0.0f; diag->ess = 0.0f; diag->status = MPPI_E_ALL_NONFINITE;
+    } else {
+        diag->eta = (float)t.eta; diag->ess = (float)(t.eta * t.eta / t.q2); diag->status = MPPI_OK;
+    }
+}
+
+// Single pass: reduce the per-wave statistics stat[0..W) into diag as reduce_stat_parts
+// does, with the list of the waves with s_w > 0 that formed partial sums, in index
+// order, with their s_w.  Done by the first wave of the calling workgroup (lane l takes
+// records l, l + 64, ...), eight records in flight per lane, so one wave builds the
+// list in order without a scan across waves.
 __device__ inline void reduce_wave_stats(const WaveStat* __restrict__ stat, int W, float lambda,
                                          int lanes, mppi_diag* __restrict__ diag,
                                          int* __restrict__ list_idx, float* __restrict__ list_s,
@@ -912,10 +1023,12 @@ __device__ __forceinline__ void update_sum_row(const float* __restrict__ S, cons
 // step: the workgroup holds both steps the interpolated knot needs, so no other
 // workgroup's result is read.  u_src is a copy of the warm start the update started
 // from (the rollout launch makes it), since u_nom is written here: workgroup j writes
-// the knot workgroup j - 1 reads.  Group d of kSumThreads threads sums control d of
-// steps j and j + 1, each row in update_sum_row's order (the same samples per thread,
-// the same reduction tree), so the results equal those of the separate sum and apply
-// launches bit for bit.
+// the knot workgroup j - 1 reads.  Every workgroup first reduces the rollout waves'
+// statistics stat[0..W) itself (the same result in each; workgroup 0 writes diag), with
+// its first costs and delta_u loads already in flight.  Group d of kSumThreads threads
+// sums control d of steps j and j + 1, each row in update_sum_row's order (the same
+// samples per thread, the same reduction tree), so the results equal those of the
+// separate statistics, sum and apply launches bit for bit.
 constexpr int kSumStepThreads = 4 * kSumThreads;
 
 __device__ __forceinline__ void update_sum_shift_step(const float* __restrict__ S,
@@ -926,30 +1039,50 @@ __device__ __forceinline__ void update_sum_shift_step(const float* __restrict__ 
                                                       float* __restrict__ u_nom,
                                                       float* __restrict__ u_apply, int N,
                                                       float4 u_init, float alpha,
-                                                      const mppi_diag* __restrict__ diag, int j)
+                                                      const WaveStat* __restrict__ stat, int W,
+                                                      int lanes, mppi_diag* __restrict__ diag, int j)
 {
     constexpr int nw = kSumThreads / 64;              // waves per group
     __shared__ float sh[8][nw];
     const int tid = threadIdx.x, d = tid / kSumThreads, gt = tid % kSumThreads;
     const int nr = j + 1 < N ? 2 : 1;                 // control d of step j (and j + 1)
-    const bool ok = diag->status == MPPI_OK;
+    const float* src = du + (size_t)(4 * j + d) * ld;  // row of step j; + 4 ld: step j + 1
+    const bool vec = (ld & 3) == 0;
+    const int K4 = vec ? K >> 2 : 0;
+    const float4* c4 = reinterpret_cast<const float4*>(S);
+    // Loads at clamped indices, masked where they are used: no load sits in a branch,
+    // so a batch of them is in flight together.
+    auto clamp4 = [&](int idx) { return idx < K4 ? idx : K4 - 1; };
+    float4 c0[4], a0[2][4];                           // the first iteration's operands
+    if (K4 > 0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int ic = clamp4(gt + u * kSumThreads);
+            c0[u] = c4[ic];
+#pragma unroll
+            for (int r = 0; r < 2; ++r)               // step j + 1 only if it exists
+                a0[r][u] = reinterpret_cast<const float4*>(src + (size_t)(4 * (r < nr ? r : 0)) * ld)[ic];
+        }
+    }
+    const StatSums st = reduce_stat_parts<4>(stat, W, lambda);
+    if (j == 0 && tid == 0) write_stat_diag(st, lanes, diag);
+    const bool ok = st.nf > 0;
     float acc[2] = {0.0f, 0.0f};
     float eta = 1.0f;
     if (ok) {
-        const float rho = diag->rho;
-        eta = diag->eta;
+        const float rho = st.rho;
+        eta = (float)st.eta;
         const float scale = 1.44269504089f / lambda;
         auto wt = [&](float s) { return isfinite(s) ? __builtin_amdgcn_exp2f((rho - s) * scale) : 0.0f; };
-        const float* src = du + (size_t)(4 * j + d) * ld;      // row of step j; + 4 ld: step j + 1
-        if ((ld & 3) == 0) {
-            const int K4 = K >> 2;
-            const float4* c4 = reinterpret_cast<const float4*>(S);
+        if (vec) {
             for (int i = gt; i < K4; i += 4 * kSumThreads) {   // four float4 pairs in flight
+                const bool first = i == gt;
                 float4 w[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int idx = i + u * kSumThreads;
-                    const float4 c = idx < K4 ? c4[idx] : make_float4(INFINITY, INFINITY, INFINITY, INFINITY);
+                    const float4 cl = first ? c0[u] : c4[clamp4(idx)];
+                    const float4 c = idx < K4 ? cl : make_float4(INFINITY, INFINITY, INFINITY, INFINITY);
                     w[u] = make_float4(wt(c.x), wt(c.y), wt(c.z), wt(c.w));
                 }
 #pragma unroll
@@ -960,7 +1093,8 @@ __device__ __forceinline__ void update_sum_shift_step(const float* __restrict__ 
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const int idx = i + u * kSumThreads;
-                        a[u] = idx < K4 ? s4[idx] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                        const float4 al = first ? a0[r][u] : s4[clamp4(idx)];
+                        a[u] = idx < K4 ? al : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                     }
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {

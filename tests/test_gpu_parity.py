@@ -307,6 +307,39 @@ def test_full_update_equals_stages_and_is_deterministic(lib, ctx, orc, lam):
     assert rel_err(d["eta"], d_s["eta"], 1.0) <= TOL and rel_err(d["ess"], d_s["ess"], 1.0) <= TOL
 
 
+def test_weight_statistics_do_not_depend_on_workgroup_size(lib):
+    """K = 40000 with eight lanes per sample gives 5000 wave records (more than one
+    batch per lane of each part): the reduced statistics are bit for bit the same when
+    one, four or twelve waves reduce them (one-wave kernel with 64- and 256-thread
+    workgroups, the pipe), and agree with the stage weights at the tolerance."""
+    sc = W.c2_line(K=40000, N=10)
+    P = DeviceProblem(lib, sc)
+    ctx = lib.Context(0)                     # its own capacity: the shared context stays small
+    lib.mppi_reserve(ctx, P.K, P.N, P.M)
+    diags = []
+    for shape in ((64, 8, 1, 0, 0), (256, 8, 1, 0, 0), (64, 8, 1, 0, 1)):
+        lib.mppi_set_config(ctx, P.K, P.N, P.M, *shape)
+        u_nom = P.u_nom.clone()
+        u_apply = torch.empty(8, device="cuda")
+        diag = lib.new_diag()
+        lib.mppi_update(ctx, sc.veh, sc.cost, P.solve, P.x_hat, P.x_ref, P.obs, P.M, u_nom, u_apply,
+                        diag)
+        torch.cuda.synchronize()
+        diags.append(lib.diag_from_tensor(diag))
+    for d in diags[1:]:
+        for k in ("rho", "argmin", "n_finite", "status", "eta", "ess", "lanes"):
+            assert d[k] == diags[0][k], (k, d[k], diags[0][k])
+    du, S, _ = run_rollout(lib, ctx, P, dump=False)
+    w = torch.empty(P.K, device="cuda")
+    ds = lib.new_diag()
+    lib.mppi_weights(ctx, P.K, S, P.solve["lam"], w, ds)
+    torch.cuda.synchronize()
+    d_s = lib.diag_from_tensor(ds)
+    assert diags[0]["rho"] == d_s["rho"] and diags[0]["argmin"] == d_s["argmin"]
+    assert rel_err(diags[0]["eta"], d_s["eta"], 1.0) <= TOL
+    assert rel_err(diags[0]["ess"], d_s["ess"], 1.0) <= TOL
+
+
 def test_update_writes_pinned_host_output(lib, ctx):
     """u_apply in pinned host memory (through mppi_device_address): the command lands
     on the host without a copy, bit for bit the device-memory result, over consecutive
