@@ -93,8 +93,6 @@ __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
     if (tail.u_copy && blockIdx.x == 0)   // the warm start, for the sum launch that rewrites it
         for (int i = threadIdx.x; i < 4 * a.N; i += blockDim.x) tail.u_copy[i] = u_nom[i];
     const float phx = x_hat[0], phy = x_hat[1], phz = x_hat[2];
-    stage_obstacles(obs_lds, obs, a.M, phx, phy, phz, a.cp.margin);
-    __syncthreads();
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int nch = (a.N + kPipeChunk - 1) / kPipeChunk;
     constexpr int kO = 4;                 // first obstacle wave
@@ -107,6 +105,13 @@ __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
     const bool valid = k < a.K;
     const int kk = valid ? k : a.K - 1;
     const bool writer = valid && q == 0;
+    float up[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    // The noise role runs one chunk ahead of the rates role: its first chunk is drawn
+    // while the other waves stage the obstacles (the staging work is shifted off wave 0).
+    stage_obstacles(obs_lds, obs, a.M, phx, phy, phz, a.cp.margin, (int)blockDim.x - 64, [&]() {
+        if (wv == 0) pipe_noise_chunk<!kFused>(a, u_nom, du_out, writer, kk, 0, up, P, lane);
+    });
+    __syncthreads();
 
     State x;
     x.px = 0.0f; x.py = 0.0f; x.pz = 0.0f;
@@ -114,41 +119,42 @@ __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
     x.vx = x_hat[7]; x.vy = x_hat[8]; x.vz = x_hat[9];
     x.wx = x_hat[10]; x.wy = x_hat[11]; x.wz = x_hat[12];
     x.T0 = x_hat[13]; x.T1 = x_hat[14]; x.T2 = x_hat[15]; x.T3 = x_hat[16];
-    float up[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     KahanSum S;
     int tested = 0;
     const float4 oh = obs_lds[0];          // obstacle block header
     if (wv >= kO)                          // state j = 0 is scored too (Eq. (17))
         S.add(state_cost<L, U>(a.cp, x, x_ref, phx, phy, phz, oh, obs_lds, a.M, q, tested));
 
-    // Each role runs its own loop over the nch + kO phases, with one workgroup barrier
-    // per phase in every loop (the barrier counts waves, not code locations), so that
-    // only the role's own parameters are live in its loop.
-    const int nph = nch + kO;
+    // Each role runs its own loop over the nch + kO - 1 phases (chunk c: noise in phase
+    // c - 1, its first chunk during the staging; rates in phase c, attitude c + 1,
+    // translation c + 2, obstacles c + 3), with one workgroup barrier per phase in every
+    // loop (the barrier counts waves, not code locations), so that only the role's own
+    // parameters are live in its loop.
+    const int nph = nch + kO - 1;
     if (wv == 0) {
         for (int ph = 0; ph < nph; ++ph) {
-            if (ph < nch) pipe_noise_chunk<!kFused>(a, u_nom, du_out, writer, kk, ph, up, P, lane);
+            if (ph + 1 < nch) pipe_noise_chunk<!kFused>(a, u_nom, du_out, writer, kk, ph + 1, up, P, lane);
             __syncthreads();
         }
     } else if (wv == 1) {
         for (int ph = 0; ph < nph; ++ph) {
-            if (ph >= 1 && ph < nch + 1) pipe_rates_chunk<kLag>(a, x, ph - 1, P, lane);
+            if (ph < nch) pipe_rates_chunk<kLag>(a, x, ph, P, lane);
             __syncthreads();
         }
     } else if (wv == 2) {
         for (int ph = 0; ph < nph; ++ph) {
-            if (ph >= 2 && ph < nch + 2) pipe_attitude_chunk(a, x, ph - 2, P, lane);
+            if (ph >= 1 && ph < nch + 1) pipe_attitude_chunk(a, x, ph - 1, P, lane);
             __syncthreads();
         }
     } else if (wv == 3) {
         for (int ph = 0; ph < nph; ++ph) {
-            if (ph >= 3 && ph < nch + 3)
-                pipe_translation_chunk<L>(a, x_ref, oh, obs_lds, phx, phy, phz, x, ph - 3, lane, P);
+            if (ph >= 2 && ph < nch + 2)
+                pipe_translation_chunk<L>(a, x_ref, oh, obs_lds, phx, phy, phz, x, ph - 2, lane, P);
             __syncthreads();
         }
     } else {
         for (int ph = 0; ph < nph; ++ph) {
-            if (ph >= kO) pipe_obstacle_chunk<L, U>(a, obs_lds, S, tested, ph - kO, sb, q, wv - kO, P);
+            if (ph >= kO - 1) pipe_obstacle_chunk<L, U>(a, obs_lds, S, tested, ph - (kO - 1), sb, q, wv - kO, P);
             __syncthreads();
         }
     }

@@ -24,11 +24,21 @@ namespace mppi {
 // (rank sort: each obstacle's rank is the number of obstacles before it in (x, index)
 // order) and indexed by kObsBins bins; otherwise they keep their order and culling is
 // off.  Contains barriers: every thread of the workgroup calls it; the caller
-// synchronises again before reading the block.
+// synchronises again before reading the block.  The work is spread over thread indices
+// shifted by tshift (mod the workgroup size), and every thread calls hook() once after
+// the first barrier: a caller can keep one wave free of staging work and give it
+// other work there.
+struct NoStageHook {
+    __device__ void operator()() const {}
+};
+
+template <typename Hook = NoStageHook>
 __device__ __forceinline__ void stage_obstacles(float4* blk, const mppi_obstacle* __restrict__ obs,
-                                                int M, float phx, float phy, float phz, float margin)
+                                                int M, float phx, float phy, float phz, float margin,
+                                                int tshift = 0, const Hook& hook = Hook())
 {
     __shared__ unsigned int s_rmax;
+    const int t = (int)((threadIdx.x + (unsigned)tshift) % blockDim.x);
     float4* o_lds = blk + kObsHeaderFloat4;
     int* bins = reinterpret_cast<int*>(blk + 1);
     const bool cull = M >= kCullMin && M <= kCullMax;
@@ -40,20 +50,21 @@ __device__ __forceinline__ void stage_obstacles(float4* blk, const mppi_obstacle
         o_lds[2 * rank + 1] = make_float4(o.r * o.r, R * R, R, 0.0f);
         atomicMax(&s_rmax, __float_as_uint(fmaxf(R, 0.0f)));
     };
-    if (threadIdx.x == 0) s_rmax = 0u;
+    if (t == 0) s_rmax = 0u;
     if (cull && M >= kCullKeysInLds) {
         // long lists: the sort keys (x relative to p_hat) go to LDS first, where the
         // obstacles land afterwards, padded to whole float4 with +inf, and each rank
         // reads them four at a time (a global load per obstacle costs more)
         float* keys = reinterpret_cast<float*>(o_lds);
         const int M4 = (M + 3) >> 2;
-        for (int j = threadIdx.x; j < 4 * M4; j += blockDim.x)
+        for (int j = t; j < 4 * M4; j += blockDim.x)
             keys[j] = j < M ? obs[j].c[0] - phx : INFINITY;
         __syncthreads();
+        hook();
         int ranks[kCullMax / 64];                       // blockDim >= 64
 #pragma unroll
         for (int n = 0; n < kCullMax / 64; ++n) {
-            const int i = threadIdx.x + n * blockDim.x;
+            const int i = t + n * blockDim.x;
             ranks[n] = 0;
             if (i < M) {
                 const float key = keys[i];
@@ -71,12 +82,13 @@ __device__ __forceinline__ void stage_obstacles(float4* blk, const mppi_obstacle
         __syncthreads();                                // keys read; the obstacles land
 #pragma unroll
         for (int n = 0; n < kCullMax / 64; ++n) {
-            const int i = threadIdx.x + n * blockDim.x;
+            const int i = t + n * blockDim.x;
             if (i < M) put(i, ranks[n]);
         }
     } else {
         __syncthreads();                                // s_rmax set
-        for (int i = threadIdx.x; i < M; i += blockDim.x) {
+        hook();
+        for (int i = t; i < M; i += blockDim.x) {
             int rank = i;
             if (cull) {                                 // short lists: keys from global
                 const float key = obs[i].c[0] - phx;
@@ -89,7 +101,7 @@ __device__ __forceinline__ void stage_obstacles(float4* blk, const mppi_obstacle
             put(i, rank);
         }
     }
-    for (int i = threadIdx.x; i < kObsPad; i += blockDim.x) {
+    for (int i = t; i < kObsPad; i += blockDim.x) {
         const int m = (M > 0 ? M : 0) + i;
         o_lds[2 * m] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         o_lds[2 * m + 1] = make_float4(-INFINITY, -INFINITY, 0.0f, 0.0f);
@@ -99,7 +111,7 @@ __device__ __forceinline__ void stage_obstacles(float4* blk, const mppi_obstacle
     if (cull) {
         x0 = o_lds[0].x;
         w = fmaxf((o_lds[2 * (M - 1)].x - x0) * (1.0f / kObsBins), 1.0e-3f);
-        for (int bb = threadIdx.x; bb <= kObsBins; bb += blockDim.x) {
+        for (int bb = t; bb <= kObsBins; bb += blockDim.x) {
             int idx = M;
             if (bb < kObsBins) {                     // first obstacle with x >= x0 + bb w
                 const float edge = x0 + (float)bb * w;
@@ -113,7 +125,7 @@ __device__ __forceinline__ void stage_obstacles(float4* blk, const mppi_obstacle
             bins[bb] = idx;
         }
     }
-    if (threadIdx.x == 0)
+    if (t == 0)
         blk[0] = make_float4(x0, 1.0f / w, __uint_as_float(s_rmax) + kCullSlack, cull ? 1.0f : 0.0f);
 }
 
@@ -1064,6 +1076,10 @@ __device__ __forceinline__ void update_sum_shift_step(const float* __restrict__ 
                 a0[r][u] = reinterpret_cast<const float4*>(src + (size_t)(4 * (r < nr ? r : 0)) * ld)[ic];
         }
     }
+    float us[8];                                      // u_src of steps j and j + 1, for thread 0
+    if (tid == 0)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) us[r] = u_src[4 * j + (r < 4 * nr ? r : 0)];
     const StatSums st = reduce_stat_parts<4>(stat, W, lambda);
     if (j == 0 && tid == 0) write_stat_diag(st, lanes, diag);
     const bool ok = st.nf > 0;
@@ -1126,6 +1142,7 @@ __device__ __forceinline__ void update_sum_shift_step(const float* __restrict__ 
     if (tid != 0) return;
     const float init[4] = {u_init.x, u_init.y, u_init.z, u_init.w};
     float up[8];                                      // u_upd of steps j (0..3) and j + 1 (4..7)
+#pragma unroll
     for (int r = 0; r < 8; ++r) {
         if (r >= 4 * nr) {
             up[r] = init[r - 4];
@@ -1134,7 +1151,7 @@ __device__ __forceinline__ void update_sum_shift_step(const float* __restrict__ 
         float t = 0.0f;
         if (ok)
             for (int i = 0; i < nw; ++i) t += sh[r][i];
-        up[r] = ok ? u_src[4 * j + r] + t / eta : u_src[4 * j + r];
+        up[r] = ok ? us[r] + t / eta : us[r];
     }
     if (j == 0) {
         for (int c = 0; c < 4; ++c) u_apply[c] = up[c];
