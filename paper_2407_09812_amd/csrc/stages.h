@@ -453,6 +453,90 @@ __device__ __forceinline__ void twosum_merge(float& s, float& c, float s2, float
     c = c + c2 + e;
 }
 
+// Deterministic reductions over the 64 lanes of a wave (all lanes active), read from
+// lane 63: a butterfly within each row of 16 lanes by DPP moves (quad permutations xor
+// 1 and xor 2, half-row mirror, row mirror), then the row broadcasts 15 and 31 fold the
+// rows into lane 63.  Lanes a step does not write receive the operation's identity.
+// No LDS traffic: each step is one VALU move.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int dpp_i(int x, int identity)
+{
+    return __builtin_amdgcn_update_dpp(identity, x, kCtrl, kRowMask, 0xF, false);
+}
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ float dpp_f(float x, float identity)
+{
+    return __int_as_float(dpp_i<kCtrl, kRowMask>(__float_as_int(x), __float_as_int(identity)));
+}
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_d(double x)      // identity 0.0
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_i<kCtrl, kRowMask>((int)(unsigned)(b & 0xffffffffll), 0);
+    const int hi = dpp_i<kCtrl, kRowMask>((int)(b >> 32), 0);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ float lane63(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ int lane63(int v) { return __builtin_amdgcn_readlane(v, 63); }
+__device__ __forceinline__ double lane63(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffll), 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+#define MPPI_WAVE_STEPS(STEP) STEP(0xB1, 0xF) STEP(0x4E, 0xF) STEP(0x141, 0xF) STEP(0x140, 0xF) \
+                              STEP(0x142, 0xA) STEP(0x143, 0xC)
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#define MPPI_STEP(C, R) v += dpp_f<C, R>(v, 0.0f);
+    MPPI_WAVE_STEPS(MPPI_STEP)
+#undef MPPI_STEP
+    return lane63(v);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#define MPPI_STEP(C, R) v += dpp_d<C, R>(v);
+    MPPI_WAVE_STEPS(MPPI_STEP)
+#undef MPPI_STEP
+    return lane63(v);
+}
+
+// (value, index) minimum with argmin_merge and the sum of n over the wave.
+__device__ __forceinline__ void wave_argmin_count(float& v, int& i, int& n)
+{
+#define MPPI_STEP(C, R)                                                          \
+    {                                                                            \
+        const float v2 = dpp_f<C, R>(v, INFINITY);                               \
+        const int i2 = dpp_i<C, R>(i, INT_MAX);                                  \
+        argmin_merge(v, i, v2, i2);                                              \
+        n += dpp_i<C, R>(n, 0);                                                  \
+    }
+    MPPI_WAVE_STEPS(MPPI_STEP)
+#undef MPPI_STEP
+    v = lane63(v); i = lane63(i); n = lane63(n);
+}
+
+// Compensated (two-sum) total of (s, c) pairs and the plain sum q over the wave.
+__device__ __forceinline__ void wave_twosum(float& s, float& c, float& q)
+{
+#define MPPI_STEP(C, R)                                                          \
+    {                                                                            \
+        const float s2 = dpp_f<C, R>(s, 0.0f), c2 = dpp_f<C, R>(c, 0.0f);        \
+        twosum_merge(s, c, s2, c2);                                              \
+        q += dpp_f<C, R>(q, 0.0f);                                               \
+    }
+    MPPI_WAVE_STEPS(MPPI_STEP)
+#undef MPPI_STEP
+    s = lane63(s); c = lane63(c); q = lane63(q);
+}
+
 // ---------------------------------------------------------------------------
 // G2: softmin weights
 // ---------------------------------------------------------------------------
@@ -637,23 +721,12 @@ __device__ __forceinline__ WaveSums wave_sums(float S, int k, int q, bool valid,
     float mv = fin ? S : INFINITY;
     int mi = fin ? k : INT_MAX;
     int nf = (fin && q == 0) ? 1 : 0;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const float v2 = __shfl_xor(mv, off);
-        const int i2 = __shfl_xor(mi, off);
-        argmin_merge(mv, mi, v2, i2);
-        nf += __shfl_xor(nf, off);
-    }
+    wave_argmin_count(mv, mi, nf);
     w.rho = mv; w.argmin = mi; w.n = nf;
     const float scale = 1.44269504089f / lambda;
     w.e = fin ? __builtin_amdgcn_exp2f((mv - S) * scale) : 0.0f;
     float es = q == 0 ? w.e : 0.0f, ec = 0.0f, q2 = es * es;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const float s2 = __shfl_xor(es, off), c2 = __shfl_xor(ec, off);
-        twosum_merge(es, ec, s2, c2);
-        q2 += __shfl_xor(q2, off);
-    }
+    wave_twosum(es, ec, q2);
     w.es = es; w.ec = ec; w.q2 = q2;
     return w;
 }
@@ -835,13 +908,7 @@ __device__ inline StatSums reduce_stat_parts(const WaveStat* __restrict__ stat, 
                 if (r[u].n > 0) argmin_merge(mv, mi, r[u].rho, r[u].argmin);
             }
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const float v2 = __shfl_xor(mv, off);
-            const int i2 = __shfl_xor(mi, off);
-            argmin_merge(mv, mi, v2, i2);
-            nf += __shfl_xor(nf, off);
-        }
+        wave_argmin_count(mv, mi, nf);
         if (lane == 0) { sh_v[p] = mv; sh_i[p] = mi; sh_n[p] = nf; }
     }
     __syncthreads();
@@ -865,11 +932,8 @@ __device__ inline StatSums reduce_stat_parts(const WaveStat* __restrict__ stat, 
                 }
             }
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            eta += __shfl_xor(eta, off);
-            q2 += __shfl_xor(q2, off);
-        }
+        eta = wave_sum(eta);
+        q2 = wave_sum(q2);
         if (lane == 0) { sh_eta[p] = eta; sh_q[p] = q2; }
     }
     __syncthreads();
@@ -1019,8 +1083,7 @@ __device__ __forceinline__ void update_sum_row(const float* __restrict__ S, cons
     } else {
         for (int k = tid; k < K; k += blockDim.x) acc = fmaf(src[k], wt(S[k]), acc);
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    acc = wave_sum(acc);
     if ((tid & 63) == 0) sh[tid >> 6] = acc;
     __syncthreads();
     if (tid == 0) {
@@ -1133,8 +1196,7 @@ __device__ __forceinline__ void update_sum_shift_step(const float* __restrict__ 
         }
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) acc[r] += __shfl_xor(acc[r], off);
+            acc[r] = wave_sum(acc[r]);
             if ((gt & 63) == 0) sh[4 * r + d][gt >> 6] = acc[r];
         }
         __syncthreads();
