@@ -336,6 +336,32 @@ def mppi_update(ctx, veh, cst, slv, x_hat, x_ref, obs_dev, M, u_nom, u_apply, di
                                _ptr(u_nom), _ptr(u_apply), _ptr(diag)), "mppi_update")
 
 
+class PreparedUpdate:
+    """mppi_update with its arguments marshalled once: calling it (no arguments) runs
+    the update on the same buffers, for a control loop that holds its per-step inputs in
+    fixed device buffers, as a C caller holds its pointers.  The buffers' contents may
+    change between calls; the tensors must stay alive."""
+
+    def __init__(self, ctx, veh, cst, slv, x_hat, x_ref, obs_dev, M, u_nom, u_apply, diag=None,
+                 stream=None):
+        self._ctx = ctx
+        self._keep = (vehicle(veh), cost(cst), solve(slv), x_hat, x_ref, obs_dev, u_nom, u_apply, diag)
+        v, c, s = self._keep[:3]
+        self._args = (ctx.handle, _stream(stream), C.byref(v), C.byref(c), C.byref(s), _ptr(x_hat),
+                      _ptr(x_ref), _ptr(obs_dev) if M > 0 else None, int(M), _ptr(u_nom),
+                      _ptr(u_apply), _ptr(diag))
+
+    def __call__(self):
+        st = _lib.mppi_update(*self._args)
+        if st != MPPI_OK:
+            self._ctx.check(st, "mppi_update")
+
+
+def prepare_update(ctx, veh, cst, slv, x_hat, x_ref, obs_dev, M, u_nom, u_apply, diag=None,
+                   stream=None) -> PreparedUpdate:
+    return PreparedUpdate(ctx, veh, cst, slv, x_hat, x_ref, obs_dev, M, u_nom, u_apply, diag, stream)
+
+
 def mppi_rollout(ctx, veh, cst, slv, x_hat, x_ref, obs_dev, M, u_nom, du, ld, S, states=None,
                  stream=None):
     v, c, s = vehicle(veh), cost(cst), solve(slv)

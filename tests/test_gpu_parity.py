@@ -340,6 +340,32 @@ def test_weight_statistics_do_not_depend_on_workgroup_size(lib):
     assert rel_err(diags[0]["ess"], d_s["ess"], 1.0) <= TOL
 
 
+def test_prepared_update_equals_update(lib, ctx):
+    """lib.prepare_update marshals the arguments once; calling it twice gives what two
+    mppi_update calls on the same buffers give, bit for bit, and it reads the buffers'
+    current contents at each call."""
+    sc = W.c2_line(K=512, N=30)
+    P = DeviceProblem(lib, sc)
+    outs = []
+    for prepared in (False, True):
+        u_nom, u_apply, diag = P.u_nom.clone(), torch.empty(8, device="cuda"), lib.new_diag()
+        x_hat = P.x_hat.clone()
+        call = (lib.prepare_update(ctx, sc.veh, sc.cost, P.solve, x_hat, P.x_ref, P.obs, P.M,
+                                   u_nom, u_apply, diag) if prepared else
+                (lambda: lib.mppi_update(ctx, sc.veh, sc.cost, P.solve, x_hat, P.x_ref, P.obs, P.M,
+                                         u_nom, u_apply, diag)))
+        call()
+        x_hat[0] += 0.5                          # the second call sees the new state
+        call()
+        torch.cuda.synchronize()
+        outs.append((u_nom.cpu(), u_apply.cpu(), diag.cpu()))
+    assert all(torch.equal(a, b) for a, b in zip(outs[0], outs[1]))
+    bad = dict(P.solve, lam=-1.0)
+    with pytest.raises(lib.MPPIError):
+        lib.prepare_update(ctx, sc.veh, sc.cost, bad, P.x_hat, P.x_ref, P.obs, P.M, P.u_nom,
+                           torch.empty(8, device="cuda"))()
+
+
 def test_update_writes_pinned_host_output(lib, ctx):
     """u_apply in pinned host memory (through mppi_device_address): the command lands
     on the host without a copy, bit for bit the device-memory result, over consecutive
