@@ -22,12 +22,15 @@ namespace mppi {
 // which keeps binary32 rounding at the scale of the excursion rather than of the
 // world frame.  For kCullMin <= M <= kCullMax the obstacles are placed in order of x
 // (rank sort: each obstacle's rank is the number of obstacles before it in (x, index)
-// order) and indexed by kObsBins bins; otherwise they keep their order and culling is
-// off.  Contains barriers: every thread of the workgroup calls it; the caller
+// order; short lists rank within one wave, lane j holding key j, long lists read the
+// keys from LDS) and indexed by kObsBins bins; otherwise they keep their order and
+// culling is off.  Contains barriers: every thread of the workgroup calls it; the caller
 // synchronises again before reading the block.  The work is spread over thread indices
 // shifted by tshift (mod the workgroup size), and every thread calls hook() once after
 // the first barrier: a caller can keep one wave free of staging work and give it
 // other work there.
+static_assert(kCullKeysInLds <= 64, "short obstacle lists are ranked within one wave");
+
 struct NoStageHook {
     __device__ void operator()() const {}
 };
@@ -42,23 +45,36 @@ __device__ __forceinline__ void stage_obstacles(float4* blk, const mppi_obstacle
     float4* o_lds = blk + kObsHeaderFloat4;
     int* bins = reinterpret_cast<int*>(blk + 1);
     const bool cull = M >= kCullMin && M <= kCullMax;
-    auto put = [&](int i, int rank) {
-        const mppi_obstacle o = obs[i];
+    auto place = [&](const mppi_obstacle& o, int rank) {
         const float R = o.r + margin;
         o_lds[2 * rank] = make_float4(o.c[0] - phx, o.c[1] - phy, o.c[2] - phz,
                                       o.type == MPPI_VCYLINDER ? 0.0f : 1.0f);
         o_lds[2 * rank + 1] = make_float4(o.r * o.r, R * R, R, 0.0f);
-        atomicMax(&s_rmax, __float_as_uint(fmaxf(R, 0.0f)));
+    };
+    auto put = [&](int i, int rank) {
+        const mppi_obstacle o = obs[i];
+        place(o, rank);
+        atomicMax(&s_rmax, __float_as_uint(fmaxf(o.r + margin, 0.0f)));
     };
     if (t == 0) s_rmax = 0u;
     if (cull && M >= kCullKeysInLds) {
         // long lists: the sort keys (x relative to p_hat) go to LDS first, where the
         // obstacles land afterwards, padded to whole float4 with +inf, and each rank
         // reads them four at a time (a global load per obstacle costs more)
+        // Each thread loads its obstacles i = t + n blockDim once, keeps them in registers
+        // for the placement, and writes their keys.
         float* keys = reinterpret_cast<float*>(o_lds);
         const int M4 = (M + 3) >> 2;
-        for (int j = t; j < 4 * M4; j += blockDim.x)
-            keys[j] = j < M ? obs[j].c[0] - phx : INFINITY;
+        mppi_obstacle mine[kCullMax / 64];
+#pragma unroll
+        for (int n = 0; n < kCullMax / 64; ++n) {
+            const int i = t + n * blockDim.x;
+            if (i < M) {
+                mine[n] = obs[i];
+                keys[i] = mine[n].c[0] - phx;
+            }
+        }
+        for (int j = M + t; j < 4 * M4; j += blockDim.x) keys[j] = INFINITY;
         __syncthreads();
         hook();
         int ranks[kCullMax / 64];                       // blockDim >= 64
@@ -80,26 +96,38 @@ __device__ __forceinline__ void stage_obstacles(float4* blk, const mppi_obstacle
             }
         }
         __syncthreads();                                // keys read; the obstacles land
+        float rmax = 0.0f;
 #pragma unroll
         for (int n = 0; n < kCullMax / 64; ++n) {
             const int i = t + n * blockDim.x;
-            if (i < M) put(i, ranks[n]);
+            if (i < M) {
+                place(mine[n], ranks[n]);
+                rmax = fmaxf(rmax, fmaxf(mine[n].r + margin, 0.0f));
+            }
         }
-    } else {
+        float lo, hi;                                   // one atomic per wave
+        wave_range(rmax, lo, hi);
+        if ((threadIdx.x & 63) == 0) atomicMax(&s_rmax, __float_as_uint(hi));
+    } else if (cull) {                                  // short lists (M < 64): one wave
         __syncthreads();                                // s_rmax set
         hook();
-        for (int i = t; i < M; i += blockDim.x) {
-            int rank = i;
-            if (cull) {                                 // short lists: keys from global
-                const float key = obs[i].c[0] - phx;
-                rank = 0;
-                for (int j = 0; j < M; ++j) {
-                    const float kj = obs[j].c[0] - phx;
-                    rank += (kj < key || (kj == key && j < i)) ? 1 : 0;
-                }
+        if (t < 64) {                                   // the whole wave of t in [0, 64)
+            const mppi_obstacle o = obs[t < M ? t : 0];  // one load per lane, kept
+            const float key = t < M ? o.c[0] - phx : INFINITY;
+            int rank = 0;
+            for (int j = 0; j < M; ++j) {               // key j broadcast from lane j
+                const float kj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(key), j));
+                rank += (kj < key || (kj == key && j < t)) ? 1 : 0;
             }
-            put(i, rank);
+            if (t < M) place(o, rank);
+            float lo, hi;                               // R_max over the wave, no atomics
+            wave_range(t < M ? fmaxf(o.r + margin, 0.0f) : 0.0f, lo, hi);
+            if (t == 0) s_rmax = __float_as_uint(hi);
         }
+    } else {                                            // order kept, culling off
+        __syncthreads();                                // s_rmax set
+        hook();
+        for (int i = t; i < M; i += blockDim.x) put(i, i);
     }
     for (int i = t; i < kObsPad; i += blockDim.x) {
         const int m = (M > 0 ? M : 0) + i;
