@@ -316,6 +316,14 @@ __device__ __forceinline__ void pipe_noise_chunk(const RolloutParams& a, const f
                                                  int c, float (&up)[4], PipeLds& P, int lane)
 {
     const size_t ld = (size_t)a.ld;
+    float un[kPipeChunk][4];                                   // the chunk's u_nom rows, loaded
+#pragma unroll                                                 // together (the last clamped)
+    for (int s = 0; s < kPipeChunk; ++s) {
+        const int j = c * kPipeChunk + s < a.N ? c * kPipeChunk + s : a.N - 1;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) un[s][d] = u_nom[4 * j + d];
+    }
+#pragma unroll
     for (int s = 0; s < kPipeChunk; ++s) {
         const int j = c * kPipeChunk + s;
         if (j >= a.N) break;                                   // uniform
@@ -327,7 +335,7 @@ __device__ __forceinline__ void pipe_noise_chunk(const RolloutParams& a, const f
             for (int d = 0; d < 4; ++d) dst[(size_t)d * ld] = du[d];
         }
 #pragma unroll
-        for (int d = 0; d < 4; ++d) u[d] = u_nom[4 * j + d] + du[d];
+        for (int d = 0; d < 4; ++d) u[d] = un[s][d] + du[d];
         float cu = 0.0f;
 #pragma unroll
         for (int d = 0; d < 4; ++d) cu = fmaf(a.cp.R[d] * u[d], u[d], cu);
