@@ -1129,12 +1129,12 @@ __device__ __forceinline__ void update_sum_row(const float* __restrict__ S, cons
     }
 }
 
-// Weighted sums of step j's rows and of step j + 1's (Eq. (5)), then the apply and
-// advance of knot j (Algorithm 1; Sec. IV-B), one workgroup of kSumStepThreads per
-// step: the workgroup holds both steps the interpolated knot needs, so no other
-// workgroup's result is read.  u_src is a copy of the warm start the update started
-// from (the rollout launch makes it), since u_nom is written here: workgroup j writes
-// the knot workgroup j - 1 reads.  Every workgroup first reduces the rollout waves'
+// Weighted sums of step j's rows (Eq. (5)), then the apply and advance (Algorithm 1;
+// Sec. IV-B), one workgroup of kSumStepThreads per step j.  With the plain shift
+// (alpha = 1) workgroup j writes knot j - 1 (= step j's update) and the last also the
+// refilled knot N - 1; with interpolation it also sums step j + 1's rows and writes knot
+// j, so no workgroup reads another's result.  u_src is a copy of the warm start the
+// update started from (the rollout launch makes it), since u_nom is written here.  Every workgroup first reduces the rollout waves'
 // statistics stat[0..W) itself (the same result in each; workgroup 0 writes diag), with
 // its first costs and delta_u loads already in flight.  Group d of kSumThreads threads
 // sums control d of steps j and j + 1, each row in update_sum_row's order (the same
@@ -1156,7 +1156,8 @@ __device__ __forceinline__ void update_sum_shift_step(const float* __restrict__ 
     constexpr int nw = kSumThreads / 64;              // waves per group
     __shared__ float sh[8][nw];
     const int tid = threadIdx.x, d = tid / kSumThreads, gt = tid % kSumThreads;
-    const int nr = j + 1 < N ? 2 : 1;                 // control d of step j (and j + 1)
+    const bool shift = alpha == 1.0f;
+    const int nr = !shift && j + 1 < N ? 2 : 1;       // control d of step j (and j + 1)
     const float* src = du + (size_t)(4 * j + d) * ld;  // row of step j; + 4 ld: step j + 1
     const bool vec = (ld & 3) == 0;
     const int K4 = vec ? K >> 2 : 0;
@@ -1256,11 +1257,16 @@ __device__ __forceinline__ void update_sum_shift_step(const float* __restrict__ 
         feasible_input(P, x_hat, up, u_apply + 4);
     }
     if (!ok) return;   // all costs non-finite: keep the warm start as it was
-    // knot j moves to the value at j + alpha of the interpolant (Sec. IV-B); alpha = 1
-    // is the plain shift, copied exactly
-    const bool shift = alpha == 1.0f;
+    if (shift) {       // the plain shift, copied exactly: knot j - 1 <- step j
+        if (j > 0)
+            for (int c = 0; c < 4; ++c) u_nom[4 * (j - 1) + c] = up[c];
+        if (j == N - 1)
+            for (int c = 0; c < 4; ++c) u_nom[4 * j + c] = init[c];
+        return;
+    }
+    // knot j moves to the value at j + alpha of the interpolant (Sec. IV-B)
     const float keep = 1.0f - alpha;
-    for (int c = 0; c < 4; ++c) u_nom[4 * j + c] = shift ? up[4 + c] : fmaf(alpha, up[4 + c], keep * up[c]);
+    for (int c = 0; c < 4; ++c) u_nom[4 * j + c] = fmaf(alpha, up[4 + c], keep * up[c]);
 }
 
 // Single pass, one workgroup of kMergeThreads = 64 columns x 4 waves: u_out[col] =
