@@ -151,6 +151,34 @@ def test_pipe_edge_shapes_match_oracle(lib, ctx, orc, K, N, M, lanes):
         assert e_du <= TOL and e_S[~flips].max(initial=0.0) <= TOL and flips.sum() <= 2
 
 
+@pytest.mark.parametrize("M", [40, 160])
+def test_obstacles_with_equal_x_match_oracle(lib, ctx, orc, M):
+    """Obstacle centres on a 0.5 m grid in x, so many share their sort key: the rank
+    sort breaks ties by index (M = 40: one wave's lane-held keys; M = 160: keys in LDS),
+    every obstacle lands in its own slot and culling stays exact -- costs match the
+    oracle, which tests every obstacle, through the pipe and the one-wave kernel."""
+    rng = np.random.default_rng(M)
+    sc = W.c2_line(K=192, N=12)
+    obs = W.spheres_in_box(rng, M, (-1, -3, 0), (7, 3, 5), 0.1, 0.4)
+    obs[:, 1] = np.round(obs[:, 1] * 2.0) / 2.0
+    assert len(np.unique(obs[:, 1])) < M // 2
+    sc.obstacles = obs
+    ks = np.arange(0, sc.K, 2)
+    lib.mppi_reserve(ctx, sc.K, sc.N, sc.M)
+    P = DeviceProblem(lib, sc)
+    _, du_o, S_o = orc.rollouts_subset(P.o_veh, P.o_cost, P.o_solve, ks, P.o_x_hat, P.o_u_nom,
+                                       P.o_x_ref, P.o_obs, want_states=False)
+    kt = torch.as_tensor(ks, device="cuda")
+    for pipe, lanes in ((1, 2), (1, 8), (0, 1), (0, 4)):
+        du, S = rollout(lib, ctx, P, lanes, 1, pipe)
+        S_g = S[kt].double().cpu().numpy()
+        e_S = rel_err(S_g, S_o, 1.0)
+        flips = np.abs(np.round((S_g - S_o) / sc.cost["obs_collision"])) >= 1
+        print(f"M={M} pipe={pipe} lanes={lanes}: S {e_S[~flips].max(initial=0.0):.1e} "
+              f"collision-boundary {int(flips.sum())}")
+        assert e_S[~flips].max(initial=0.0) <= TOL and flips.sum() <= 2
+
+
 def test_pipe_longest_horizon(lib, ctx, orc):
     """N = 4096 through the pipe: costs match the oracle within binary32 drift over
     41 s of flight (1e-2, as for the one-wave kernel's states) and stay finite."""
