@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void rollout_fused_kernel(
 // last workgroup reduces the statistics with the list of contributing waves).
 static_assert(pipe_lds_bytes(kPipeMaxM) <= 160 * 1024, "the pipe's LDS must fit one gfx950 CU");
 
-template <int L, int U, bool kLag, bool kFused>
+template <int L, int U, bool kLag, bool kFused, int C>
 __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
     RolloutParams a, const float* __restrict__ x_hat, const float* __restrict__ x_ref,
     const mppi_obstacle* __restrict__ obs, const float* __restrict__ u_nom,
@@ -89,12 +89,12 @@ __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
 {
     extern __shared__ float4 lds[];       // obstacles, then PipeLds
     float4* obs_lds = lds;
-    PipeLds& P = *reinterpret_cast<PipeLds*>(lds + obstacle_lds_float4(a.M));
+    PipeLdsT<C>& P = *reinterpret_cast<PipeLdsT<C>*>(lds + obstacle_lds_float4(a.M));
     if (tail.u_copy && blockIdx.x == 0)   // the warm start, for the sum launch that rewrites it
         for (int i = threadIdx.x; i < 4 * a.N; i += blockDim.x) tail.u_copy[i] = u_nom[i];
     const float phx = x_hat[0], phy = x_hat[1], phz = x_hat[2];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int nch = (a.N + kPipeChunk - 1) / kPipeChunk;
+    const int nch = (a.N + C - 1) / C;
     constexpr int kO = 4;                 // first obstacle wave
     int sb = lane, q = 0;
     if (wv >= kO) {                       // 64 / L samples per obstacle wave
@@ -330,17 +330,27 @@ hipError_t launch_rollout_fused(const RolloutArgs& a, const LaunchConfig& c, con
     return launch_rollout_any(a, c, tail, true, stream);
 }
 
+template <int L, int U, int C>
+static hipError_t launch_pipe_luc(const RolloutArgs& a, const UpdateTail& tail, bool fused,
+                                  hipStream_t stream)
+{
+    const int grid = (a.K + 63) / 64;
+    const RolloutParams p{a.mp, a.cp, a.np, a.M, a.K, a.N, a.ld, a.obs_tests};
+    auto kernel = fused ? (a.mp.lag ? rollout_pipe_kernel<L, U, true, true, C> : rollout_pipe_kernel<L, U, false, true, C>)
+                        : (a.mp.lag ? rollout_pipe_kernel<L, U, true, false, C> : rollout_pipe_kernel<L, U, false, false, C>);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(64 * (4 + L)), pipe_lds_bytes<C>(a.M), stream, p, a.x_hat,
+                       a.x_ref, a.obs, a.u_nom, a.du, a.S, tail);
+    return hipGetLastError();
+}
+
+// Chunks of 2 steps for short horizons: the pipeline's fill (3 phases) is a smaller
+// share of the few chunks there are.
 template <int L, int U>
 static hipError_t launch_pipe_lu(const RolloutArgs& a, const UpdateTail& tail, bool fused,
                                  hipStream_t stream)
 {
-    const int grid = (a.K + 63) / 64;
-    const RolloutParams p{a.mp, a.cp, a.np, a.M, a.K, a.N, a.ld, a.obs_tests};
-    auto kernel = fused ? (a.mp.lag ? rollout_pipe_kernel<L, U, true, true> : rollout_pipe_kernel<L, U, false, true>)
-                        : (a.mp.lag ? rollout_pipe_kernel<L, U, true, false> : rollout_pipe_kernel<L, U, false, false>);
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(64 * (4 + L)), pipe_lds_bytes(a.M), stream, p, a.x_hat,
-                       a.x_ref, a.obs, a.u_nom, a.du, a.S, tail);
-    return hipGetLastError();
+    return a.N <= kPipeShortN ? launch_pipe_luc<L, U, 2>(a, tail, fused, stream)
+                              : launch_pipe_luc<L, U, kPipeChunk>(a, tail, fused, stream);
 }
 
 template <int L>

@@ -286,46 +286,50 @@ __device__ __forceinline__ float rollout_sample(const RolloutParams& a, const fl
 // rates, wave 2 the attitude and the stage accelerations, wave 3 integrates p and v
 // and scores the tracking cost, and waves 4 .. 4 + L - 1 score the obstacles and sum
 // the running cost (L lanes per sample dividing the obstacle tests, as in
-// rollout_sample).  The roles hand over chunks of kPipeChunk steps through
+// rollout_sample).  The roles hand over chunks of C steps (kPipeChunk, or 2 for
+// horizons up to kPipeShortN steps: a shorter fill) through
 // double-buffered LDS, one workgroup barrier per chunk, each role one chunk behind the
 // previous.  The arithmetic is rollout_sample's, operation for operation (the values
 // handed between chains pass through opaque() in both).
 // ---------------------------------------------------------------------------
 
-constexpr int kPipeChunk = 4;
+constexpr int kPipeChunk = 4;        // steps per chunk (2 for short horizons)
+constexpr int kPipeShortN = 24;      // horizons up to this many steps use chunks of 2
 
-struct PipeLds {
-    float4 u[2][kPipeChunk][64];         // u_j per sample
-    float cu[2][kPipeChunk][64];         // input and input-change cost of step j
-    float4 w[2][kPipeChunk][5][64];      // stage rates x, y, z, stage thrust F, (omega, cost)
-    float4 r[2][kPipeChunk][5][64];      // stage accelerations x, y, z, q, (omega, cost)
-    float4 p[2][kPipeChunk][64];         // p_{j+1} relative to p_hat, tracking cost
-    int2 win[2][kPipeChunk][8];          // culling window of p_{j+1} per obstacle wave
-    float cu_fwd[2][kPipeChunk][64];     // input cost, forwarded to the obstacle role
+template <int C>
+struct PipeLdsT {
+    float4 u[2][C][64];         // u_j per sample
+    float cu[2][C][64];         // input and input-change cost of step j
+    float4 w[2][C][5][64];      // stage rates x, y, z, stage thrust F, (omega, cost)
+    float4 r[2][C][5][64];      // stage accelerations x, y, z, q, (omega, cost)
+    float4 p[2][C][64];         // p_{j+1} relative to p_hat, tracking cost
+    int2 win[2][C][8];          // culling window of p_{j+1} per obstacle wave
+    float cu_fwd[2][C][64];     // input cost, forwarded to the obstacle role
 };
 
+template <int C = kPipeChunk>
 __host__ __device__ constexpr size_t pipe_lds_bytes(int M)
 {
-    return obstacle_lds_bytes(M) + sizeof(PipeLds);
+    return obstacle_lds_bytes(M) + sizeof(PipeLdsT<C>);
 }
 
 // Noise role: chunk c of sample k (kk: k clamped to K - 1).
-template <bool kStoreDu>
+template <bool kStoreDu, int C>
 __device__ __forceinline__ void pipe_noise_chunk(const RolloutParams& a, const float* __restrict__ u_nom,
                                                  float* __restrict__ du_out, bool writer, int kk,
-                                                 int c, float (&up)[4], PipeLds& P, int lane)
+                                                 int c, float (&up)[4], PipeLdsT<C>& P, int lane)
 {
     const size_t ld = (size_t)a.ld;
-    float un[kPipeChunk][4];                                   // the chunk's u_nom rows, loaded
+    float un[C][4];                                   // the chunk's u_nom rows, loaded
 #pragma unroll                                                 // together (the last clamped)
-    for (int s = 0; s < kPipeChunk; ++s) {
-        const int j = c * kPipeChunk + s < a.N ? c * kPipeChunk + s : a.N - 1;
+    for (int s = 0; s < C; ++s) {
+        const int j = c * C + s < a.N ? c * C + s : a.N - 1;
 #pragma unroll
         for (int d = 0; d < 4; ++d) un[s][d] = u_nom[4 * j + d];
     }
 #pragma unroll
-    for (int s = 0; s < kPipeChunk; ++s) {
-        const int j = c * kPipeChunk + s;
+    for (int s = 0; s < C; ++s) {
+        const int j = c * C + s;
         if (j >= a.N) break;                                   // uniform
         float du[4], u[4];
         draw_noise(a.np, (uint32_t)kk, (uint32_t)j, du);
@@ -355,12 +359,12 @@ __device__ __forceinline__ void pipe_noise_chunk(const RolloutParams& a, const f
 
 // Rates role: chunk c (x holds omega and the rotor thrusts): the controller, then
 // the body rates and thrusts at the stage points.
-template <bool kLag>
-__device__ __forceinline__ void pipe_rates_chunk(const RolloutParams& a, State& x, int c, PipeLds& P,
+template <bool kLag, int C>
+__device__ __forceinline__ void pipe_rates_chunk(const RolloutParams& a, State& x, int c, PipeLdsT<C>& P,
                                                  int lane)
 {
-    for (int s = 0; s < kPipeChunk; ++s) {
-        const int j = c * kPipeChunk + s;
+    for (int s = 0; s < C; ++s) {
+        const int j = c * C + s;
         if (j >= a.N) break;
         const float4 uv = P.u[c & 1][s][lane];
         const float u[4] = {uv.x, uv.y, uv.z, uv.w};
@@ -378,11 +382,12 @@ __device__ __forceinline__ void pipe_rates_chunk(const RolloutParams& a, State& 
 
 // Attitude role: chunk c (x holds q): q over the step from the stage rates and
 // thrusts, and the stage accelerations.
-__device__ __forceinline__ void pipe_attitude_chunk(const RolloutParams& a, State& x, int c, PipeLds& P,
+template <int C>
+__device__ __forceinline__ void pipe_attitude_chunk(const RolloutParams& a, State& x, int c, PipeLdsT<C>& P,
                                                     int lane)
 {
-    for (int s = 0; s < kPipeChunk; ++s) {
-        const int j = c * kPipeChunk + s;
+    for (int s = 0; s < C; ++s) {
+        const int j = c * C + s;
         if (j >= a.N) break;
         const float4 wx = P.w[c & 1][s][0][lane], wy = P.w[c & 1][s][1][lane];
         const float4 wz = P.w[c & 1][s][2][lane], F = P.w[c & 1][s][3][lane];
@@ -403,22 +408,22 @@ __device__ __forceinline__ void pipe_attitude_chunk(const RolloutParams& a, Stat
 // and takes the culling window of each obstacle wave's 64 / L samples (lanes of one
 // group of 64 / L here): the window that wave would take itself; hands p, that cost,
 // the input cost and the windows on to the obstacle role.
-template <int L>
+template <int L, int C>
 __device__ __forceinline__ void pipe_translation_chunk(const RolloutParams& a,
                                                        const float* __restrict__ x_ref,
                                                        const float4 oh,
                                                        const float4* __restrict__ obs_lds,
                                                        float phx, float phy, float phz, State& x,
-                                                       int c, int lane, PipeLds& P)
+                                                       int c, int lane, PipeLdsT<C>& P)
 {
     float4 h[5];                           // step s's hand-over, loaded during step s - 1
 #pragma unroll
     for (int e = 0; e < 5; ++e) h[e] = P.r[c & 1][0][e][lane];
-    for (int s = 0; s < kPipeChunk; ++s) {
-        const int j = c * kPipeChunk + s;
+    for (int s = 0; s < C; ++s) {
+        const int j = c * C + s;
         if (j >= a.N) break;
         const float4 ax = h[0], ay = h[1], az = h[2], qv = h[3], wv = h[4];
-        if (s + 1 < kPipeChunk) {
+        if (s + 1 < C) {
 #pragma unroll
             for (int e = 0; e < 5; ++e) h[e] = P.r[c & 1][s + 1][e][lane];
         }
@@ -444,20 +449,20 @@ __device__ __forceinline__ void pipe_translation_chunk(const RolloutParams& a,
 // Obstacle role (obstacle wave ow): chunk c for the sample at position sb of the
 // workgroup, lane q of its L lanes: the obstacle term at the handed-over position, and
 // the running cost in the order of rollout_sample, cu + (tracking + obstacle).
-template <int L, int U>
+template <int L, int U, int C>
 __device__ __forceinline__ void pipe_obstacle_chunk(const RolloutParams& a,
                                                     const float4* __restrict__ obs_lds,
                                                     KahanSum& S, int& tested, int c, int sb, int q,
-                                                    int ow, const PipeLds& P)
+                                                    int ow, const PipeLdsT<C>& P)
 {
     float4 h = P.p[c & 1][0][sb];
     float cu = P.cu_fwd[c & 1][0][sb];
-    for (int s = 0; s < kPipeChunk; ++s) {
-        const int j = c * kPipeChunk + s;
+    for (int s = 0; s < C; ++s) {
+        const int j = c * C + s;
         if (j >= a.N) break;
         const float4 pt = h;
         const float cj = cu;
-        if (s + 1 < kPipeChunk) {
+        if (s + 1 < C) {
             h = P.p[c & 1][s + 1][sb];
             cu = P.cu_fwd[c & 1][s + 1][sb];
         }
