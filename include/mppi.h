@@ -154,7 +154,9 @@ mppi_status mppi_validate(const mppi_vehicle *veh, const mppi_cost *cost,
 /* One full MPPI update (Algorithm 1 loop body), asynchronous on `stream`.
  *   x_hat    device, 17 floats                     state estimate
  *   x_ref    device, (N+1) x 13 floats             reference rows j = 0..N
- *   obs      device, M obstacles (may be NULL if M = 0)
+ *   obs      device, M obstacles (may be NULL if M = 0); centres and radii must be
+ *            finite (they are read on the device only: a non-finite one gives
+ *            unspecified costs, never an access outside the inputs)
  *   u_nom    device, N x 4 floats, in/out          warm start -> updated and shifted
  *   u_apply  device, 8 floats, out                 [u_nom_0 after the update (4),
  *                                                   F_clip, omega_clip at x_hat (4)]
