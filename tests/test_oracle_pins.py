@@ -123,6 +123,82 @@ def test_allocation_matrix(orc, veh):
     np.testing.assert_allclose(Gi @ np.array([mg, 0, 0, 0]), np.full(4, mg / 4), rtol=1e-15)
 
 
+def printed_allocation(l, c):
+    """Eq. (11) typed in as printed: rows [1 1 1 1], (l/sqrt2)[-1 1 1 -1],
+    (l/sqrt2)[-1 1 -1 1], c_tf[-1 -1 1 1]."""
+    s = l / math.sqrt(2.0)
+    return np.array([[1.0, 1.0, 1.0, 1.0],
+                     [-s, s, s, -s],
+                     [-s, s, -s, s],
+                     [-c, -c, c, c]])
+
+
+@pytest.mark.parametrize("l,c", [(0.15, 0.012), (0.23, 0.05)])
+def test_allocation_is_the_printed_matrix(orc, l, c):
+    """Eq. (11) element by element: a row sign flipped or two rotors swapped keeps
+    the rows orthogonal (so the checks above pass) but fails here."""
+    veh = W.vehicle_benchmark()
+    veh.update(arm_l=l, c_tf=c)
+    np.testing.assert_allclose(orc.allocation(veh), printed_allocation(l, c), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("axis,up", [(1, (1, 2)), (2, (1, 3)), (3, (2, 3))])
+def test_saturated_rotor_pattern(orc, axis, up):
+    """A large positive rate demand about one body axis from hover saturates the
+    rotors whose Eq. (11) coefficient in that torque row is positive at T_max and
+    the others at T_min (roll: rotors 2, 3; pitch: 2, 4; yaw: 3, 4, zero-based
+    indices in `up`).  The expectation is read off the printed matrix by hand, not
+    computed by the oracle."""
+    veh = W.vehicle_benchmark()
+    x = hover_state(veh)
+    u = np.array([veh["mass"] * veh["g"], 0.0, 0.0, 0.0])
+    u[axis] = 400.0                                   # rad/s: far beyond what 8 N rotors give
+    T = orc.controller(veh, x, u, 0.01)
+    want = np.full(4, veh["T_min"])
+    want[list(up)] = veh["T_max"]
+    np.testing.assert_array_equal(T, want)
+    # and the same demand negated swaps the two pairs
+    u[axis] = -400.0
+    T = orc.controller(veh, x, u, 0.01)
+    want = np.full(4, veh["T_max"])
+    want[list(up)] = veh["T_min"]
+    np.testing.assert_array_equal(T, want)
+
+
+def test_saturated_controller_from_printed_matrix(orc):
+    """Eq. (12) with partial saturation at a spinning, tilted state: the command is
+    clip(Gamma^-1 [F; J wdot_d + w x J w]) with Gamma the printed matrix of Eq. (11)
+    (numpy's solve of that matrix; the gyroscopic term written out), and the
+    feasible input of Eqs. (13)-(15) is recomposed from it through the same printed
+    matrix."""
+    veh = W.vehicle_benchmark()
+    veh.update(J=(0.012, 0.015, 0.021))
+    G = printed_allocation(veh["arm_l"], veh["c_tf"])
+    Jx, Jy, Jz = veh["J"]
+    dt = 0.01
+    rng = np.random.default_rng(11)
+    n_partial = 0
+    for _ in range(200):
+        x = hover_state(veh)
+        x[3:7] = quat_axis_angle(rng.normal(size=3), rng.uniform(0, 1))
+        wx, wy, wz = rng.normal(0, 2, 3)
+        x[10:13] = [wx, wy, wz]
+        u = np.concatenate([[rng.uniform(2, 30)], rng.normal(0, 2, 3)])
+        gyro = np.array([(Jz - Jy) * wy * wz, (Jx - Jz) * wz * wx, (Jy - Jx) * wx * wy])
+        tau_d = np.array([Jx, Jy, Jz]) * (u[1:] - x[10:13]) / dt + gyro
+        T_d = np.linalg.solve(G, np.concatenate([[u[0]], tau_d]))
+        want = np.clip(T_d, veh["T_min"], veh["T_max"])
+        T = orc.controller(veh, x, u, dt)
+        np.testing.assert_allclose(T, want, rtol=1e-12, atol=1e-12)
+        n_clip = int(np.sum((T_d < veh["T_min"]) | (T_d > veh["T_max"])))
+        n_partial += 0 < n_clip < 4
+        wrench = G @ want
+        w_clip = x[10:13] + (wrench[1:] - gyro) / np.array([Jx, Jy, Jz]) * dt
+        np.testing.assert_allclose(orc.applied_input(veh, x, u, dt),
+                                   np.concatenate([[wrench[0]], w_clip]), rtol=1e-11, atol=1e-11)
+    assert n_partial >= 10                            # saturation of some rotors, not all
+
+
 # ---------------------------------------------------------------------------
 # Controller, clipping and the feasible input (Eqs. (8)-(15))
 # ---------------------------------------------------------------------------
