@@ -501,7 +501,8 @@ def mppi_status_str(st: int) -> str:
 
 def _result_dict(r: ServerResult) -> dict:
     return dict(ticket=r.ticket, vehicle_id=r.vehicle_id, t=r.t, u_apply=np.array(r.u_apply[:]),
-                status=r.diag.status, rho=r.diag.rho, ess=r.diag.ess, argmin=r.diag.argmin,
+                status=r.diag.status, rho=r.diag.rho, eta=r.diag.eta, ess=r.diag.ess,
+                argmin=r.diag.argmin,
                 lanes=r.diag.lanes,
                 submit_s=r.submit_s, launch_s=r.launch_s, done_s=r.done_s, K=r.K, N=r.N,
                 delay=r.delay, pipe=r.pipe, latency_s=r.done_s - r.submit_s)

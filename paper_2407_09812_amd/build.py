@@ -26,8 +26,23 @@ def hipcc_flags():
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every source to an object (in parallel; each translation unit carries
+    its own device code), then link the shared library."""
+    obj_dir = os.path.join(ROOT, "_build", "mppi")
+    os.makedirs(obj_dir, exist_ok=True)
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(obj_dir, os.path.basename(src) + ".o")
+        cmd = ["hipcc", *hipcc_flags(), "-pthread", "-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd), cmd))
+        objs.append(obj)
+    failed = [cmd for p, cmd in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", *hipcc_flags(), "-shared", "-pthread", "-o", tmp, *SOURCES]
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-pthread", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -226,7 +226,16 @@ LaunchConfig heuristic_config(int K, int M)
 LaunchConfig config_for(const mppi_ctx* ctx, int K, int N, int M)
 {
     auto it = ctx->tuned.find(size_class(K, N, M));
-    return it != ctx->tuned.end() ? it->second : heuristic_config(K, M);
+    if (it == ctx->tuned.end()) return heuristic_config(K, M);
+    LaunchConfig c = it->second;
+    // A size class spans M up to the next power of two, which for 1025..2048 crosses
+    // the pipe's obstacle limit: a pipe shape stored at M <= kPipeMaxM runs past it as
+    // the one-wave kernel with the same lanes, unroll and variant.
+    if (c.pipe && M > kPipeMaxM) {
+        c.pipe = 0;
+        c.block = heuristic_config(K, M).block;
+    }
+    return c;
 }
 
 }  // namespace

@@ -90,3 +90,36 @@ def check_costs(S_gpu, S_orc, st_gpu, st_orc, obstacles, c_col, tol):
         resid = np.abs(r - np.round(r)) * c_col / np.maximum(np.abs(S_orc[ambiguous]), 1.0)
         assert resid.max() <= tol, f"ambiguous samples differ by a non-multiple of c_col: {resid.max()}"
     return e_clean, int(ambiguous.sum())
+
+
+def check_cost_flips(S_gpu, S_orc, c_col, tol, gap_orc=None, reach=None):
+    """Costs without the device's trajectories: a sample whose cost differs by at
+    least half the collision constant counts as a collision-indicator flip, and must
+    differ by an integer multiple of it (residual within tol of the cost); when the
+    oracle's closest approach to an obstacle surface per sample (gap_orc) is given,
+    a flip is allowed only where that approach is within `reach` (the distance the
+    binary32 trajectory may lie from the binary64 one) of a surface.  Returns (max
+    relative error over the other samples, number of flips)."""
+    S_gpu, S_orc = np.asarray(S_gpu, np.float64), np.asarray(S_orc, np.float64)
+    err = np.abs(S_gpu - S_orc) / np.maximum(np.abs(S_orc), 1.0)
+    if c_col > 0:
+        r = (S_gpu - S_orc) / c_col
+        flip = np.abs(r) >= 0.5
+    else:
+        r, flip = np.zeros_like(S_gpu), np.zeros(S_gpu.shape, bool)
+    if flip.any():
+        resid = np.abs(r[flip] - np.round(r[flip])) * c_col / np.maximum(np.abs(S_orc[flip]), 1.0)
+        assert resid.max() <= tol, f"flipped samples differ by a non-multiple of c_col: {resid.max()}"
+        if gap_orc is not None:
+            far = np.asarray(gap_orc)[flip] > np.asarray(reach)[flip]
+            assert not far.any(), f"{int(far.sum())} flipped samples are nowhere near a surface"
+    e_clean = err[~flip].max() if (~flip).any() else 0.0
+    return e_clean, int(flip.sum())
+
+
+def surface_gap(states, obstacles):
+    """Per sample, the smallest |distance - radius| over its states and the obstacles
+    (binary64), and a reach 2 TOL max(|p|, 1) the binary32 positions may differ by."""
+    _, gap = collision_counts(states, obstacles)
+    reach = 2.0 * TOL * np.maximum(np.linalg.norm(states[:, :, 0:3], axis=2), 1.0)
+    return gap.min(axis=1), (reach + 1e-6).max(axis=1)

@@ -48,8 +48,8 @@ def make_requests(n_req, n_veh, seed, N_max=64, M_max=40, dt_ctrl_frac=0.0, dela
     return fleet, reqs
 
 
-def new_server(lib, n_veh, n_streams=2, max_batch=4, budget=64 << 20, N_max=64):
-    veh, cost = W.vehicle_benchmark(), W.cost_benchmark()
+def new_server(lib, n_veh, n_streams=2, max_batch=4, budget=64 << 20, N_max=64, cost=None):
+    veh, cost = W.vehicle_benchmark(), (W.cost_benchmark() if cost is None else cost)
     srv = lib.Server(veh, cost, W.hover_control(veh), n_vehicles=n_veh, K_max=2048, N_max=N_max,
                      M_max=40, n_streams=n_streams, max_batch=max_batch, budget_bytes=budget)
     srv.set_batch_config(256, 0, 4, 4)           # lanes chosen per instance
@@ -221,3 +221,72 @@ def test_budget_and_argument_errors(lib):
         assert srv.stats()["rejected"] == 1
     finally:
         srv.close()
+
+
+def test_served_results_match_oracle(lib, orc):
+    """Served updates against the FP64 oracle, teacher-forced per wave: before each
+    wave the server's snapshot gives every vehicle's warm start and last served
+    command; the oracle then predicts each request's state estimate over the delay the
+    server reports with that command held (Sec. IV-E), runs the update (Algorithm 1)
+    with the interpolating advance (Sec. IV-B), and the served applied control and the
+    advanced warm start must agree at 1e-4.  The temperature is raised so that the
+    softmin's amplification of binary32 cost rounding (kappa) stays below 1e-5, checked
+    through the minimum cost the server reports.  Waves mix requests that run alone
+    (wave-specialised rollouts) and in batches (one-wave kernel).  The obstacles keep
+    their quadratic margin term but no collision constant: a state within binary32
+    reach of a surface would flip that constant and move a cost by far more than the
+    softmin tolerates at any useful temperature (the rollout tests cover the flips)."""
+    from gpu_support import f32, f32_params, rel_err
+    n_veh, N_max, lam = 8, 64, 3e5
+    fleet, reqs = make_requests(40, n_veh, seed=66, dt_ctrl_frac=0.5, delay=0.006)
+    by_vehicle = {}
+    for r in reqs:
+        by_vehicle.setdefault(r["vid"], []).append(dict(r, lam=lam))
+    waves = [[q.pop(0) for q in by_vehicle.values() if q] for _ in range(3)]
+    waves = [waves[0], waves[1][:1], waves[2]]       # all at once, one alone, all at once
+    veh, cost = W.vehicle_benchmark(), dict(W.cost_benchmark(), obs_collision=0.0)
+    o_veh, o_cost = f32_params(veh), f32_params(cost)
+    u_init = W.hover_control(veh)
+    srv = new_server(lib, n_veh, max_batch=4, cost=cost)
+    worst = dict(u_apply=0.0, u_nom=0.0, kappa=0.0)
+    shapes = set()
+    t_of = [0] * n_veh
+    try:
+        for wave in waves:
+            snap = np.frombuffer(srv.snapshot(), dtype=np.uint8)
+            nw = n_veh * N_max * 4
+            warm = snap[: 4 * nw].view(np.float32).reshape(n_veh, N_max, 4).astype(np.float64)
+            hold = snap[4 * nw: 4 * (nw + 4 * n_veh)].view(np.float32).reshape(n_veh, 4)
+            results = [srv.wait(t) for t in submit_all(lib, srv, wave)]
+            after = np.frombuffer(srv.snapshot(), dtype=np.uint8)
+            warm_after = after[: 4 * nw].view(np.float32).reshape(n_veh, N_max, 4)
+            for r, res in zip(wave, results):
+                v, K, N = r["vid"], r["K"], r["N"]
+                assert res["status"] == 0 and res["t"] == t_of[v]
+                t_of[v] += 1
+                shapes.add(res["pipe"])
+                solve = f32_params(dict(K=K, N=N, dt=r["dt"], lam=lam, sigma=r["sigma"],
+                                        u_init=u_init, seed=r["seed"], vehicle_id=v, t=res["t"],
+                                        dt_ctrl=r["dt_ctrl"]))
+                x_hat = orc.predict(o_veh, solve["dt"], float(res["delay"]), f32(r["x_hat"]),
+                                    hold[v].astype(np.float64))
+                o = orc.update(o_veh, o_cost, solve, x_hat, warm[v, :N], f32(r["x_ref"]),
+                               np.column_stack([r["obs"][:, :1], f32(r["obs"][:, 1:])]))
+                sigma = np.asarray(r["sigma"], float)
+                floors = np.concatenate([sigma, np.ones(4)])
+                worst["u_apply"] = max(worst["u_apply"],
+                                       rel_err(res["u_apply"], o["u_apply"], floors).max())
+                worst["u_nom"] = max(worst["u_nom"],
+                                     rel_err(warm_after[v, :N], o["u_nom"], sigma).max())
+                # the cost error at the minimum over lambda, and eta's relative error,
+                # which is the weighted mean of (dS_k - dS_rho) / lambda: both bound kappa
+                # from below where it matters
+                worst["kappa"] = max(worst["kappa"], abs(res["rho"] - o["diag"][0]) / lam,
+                                     rel_err(res["eta"], o["diag"][1], 1.0))
+                assert rel_err(res["ess"], o["diag"][2], 1.0) <= 1e-4
+    finally:
+        srv.close()
+    print(f"served vs oracle over {sum(len(w) for w in waves)} requests, shapes {shapes}: {worst}")
+    assert shapes == {0, 1}                           # both lone and batched requests
+    assert worst["kappa"] <= 1e-5
+    assert worst["u_apply"] <= 1e-4 and worst["u_nom"] <= 1e-4
