@@ -172,6 +172,31 @@ mppi_status mppi_update(mppi_ctx *ctx, void *stream, const mppi_vehicle *veh,
                         const mppi_obstacle *obs, int32_t M,
                         float *u_nom, float *u_apply, mppi_diag *diag);
 
+/* --- an update that allocates nothing --------------------------------------------- */
+
+/* For callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  mppi_update with its scratch
+ * (delta_u, costs, the rollout waves' weight statistics, the copy of the warm start,
+ * and the diagnostics when diag is NULL) carved out of one static device array of
+ * MPPI_STATIC_SCRATCH_BYTES on each GPU, whose address mppi_create takes on its device;
+ * the array is held until the process ends.  Needs no mppi_reserve and calls no
+ * allocating routine.  Arguments, results (bit for bit those of mppi_update in the same
+ * launch shape) and errors are mppi_update's, except that it always runs the stored
+ * form (a shape stored with fused = 1 runs with fused = 0) and that it returns
+ * MPPI_E_CAPACITY when the update needs more than the array holds: 16 N ld + 4 ld +
+ * 32 W + 16 N + 32 bytes, each part rounded up to 256, with ld = K rounded up to 64 and
+ * W the rollout launch's waves (ceil(K / 64) x lanes for the wave-specialised shape) --
+ * K = 4096, N = 100 takes 6.6 MB.  MPPI_E_HIP if the array's address could not be taken.
+ * Nothing in the array has to start at zero: each call writes what it reads.  Every
+ * call on one GPU uses that GPU's one array, which keeps the last call's contents, so
+ * calls that overlap on one GPU (other streams, contexts or threads) race: order them. */
+enum { MPPI_STATIC_SCRATCH_BYTES = 16 << 20 };
+mppi_status mppi_update_static(mppi_ctx *ctx, void *stream, const mppi_vehicle *veh,
+                               const mppi_cost *cost, const mppi_solve *solve,
+                               const float *x_hat, const float *x_ref,
+                               const mppi_obstacle *obs, int32_t M,
+                               float *u_nom, float *u_apply, mppi_diag *diag);
+
 /* --- the update's stages, exposed for stage-by-stage checking ------------------ */
 
 /* Rollouts and costs (Eqs. (2), (3)): writes delta_u [N][4][ld] (device, row

@@ -134,6 +134,7 @@ _SIGS = {
     "mppi_reserve": [_vp, _i32, _i32, _i32],
     "mppi_validate": [_PV, _PC, _PS, _i32],
     "mppi_update": [_vp, _vp, _PV, _PC, _PS, _vp, _vp, _vp, _i32, _vp, _vp, _vp],
+    "mppi_update_static": [_vp, _vp, _PV, _PC, _PS, _vp, _vp, _vp, _i32, _vp, _vp, _vp],
     "mppi_rollout": [_vp, _vp, _PV, _PC, _PS, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _vp],
     "mppi_weights": [_vp, _vp, _i32, _vp, _f32, _vp, _vp],
     "mppi_weighted_sum": [_vp, _vp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _vp],
@@ -334,6 +335,17 @@ def mppi_update(ctx, veh, cst, slv, x_hat, x_ref, obs_dev, M, u_nom, u_apply, di
     ctx.check(_lib.mppi_update(ctx.handle, _stream(stream), C.byref(v), C.byref(c), C.byref(s),
                                _ptr(x_hat), _ptr(x_ref), _ptr(obs_dev) if M > 0 else None, int(M),
                                _ptr(u_nom), _ptr(u_apply), _ptr(diag)), "mppi_update")
+
+
+def mppi_update_static(ctx, veh, cst, slv, x_hat, x_ref, obs_dev, M, u_nom, u_apply, diag=None,
+                       stream=None):
+    """mppi_update with its scratch in the library's static device array (no allocation,
+    no mppi_reserve needed; stored form)."""
+    v, c, s = vehicle(veh), cost(cst), solve(slv)
+    ctx.check(_lib.mppi_update_static(ctx.handle, _stream(stream), C.byref(v), C.byref(c),
+                                      C.byref(s), _ptr(x_hat), _ptr(x_ref),
+                                      _ptr(obs_dev) if M > 0 else None, int(M), _ptr(u_nom),
+                                      _ptr(u_apply), _ptr(diag)), "mppi_update_static")
 
 
 class PreparedUpdate:

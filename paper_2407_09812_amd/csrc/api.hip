@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -165,6 +166,68 @@ RolloutArgs rollout_args(const mppi_vehicle& v, const mppi_cost& c, const mppi_s
 
 namespace {
 
+// Device scratch of one update: the context's reserved buffers, or carved out of the
+// static array of mppi_update_static (stored form only: no single-pass buffers).
+struct Scratch {
+    float* du;               // [N][4][ld]
+    int ld;
+    float* S;                // [ld]
+    WaveStat* wstat;         // one record per rollout wave
+    float* u_upd;            // [4 N]
+    unsigned int* counters;  // single pass: two arrival counters, 0 between launches
+    float* part;             // single pass: [W][4 N]
+    unsigned int* rho_run;   // single pass: +inf between launches
+    int* list_idx;
+    float* list_s;
+    int* list_n;
+};
+
+// Scratch of mppi_update_static: one array on every GPU the library runs on, held until
+// the process ends.  Host code never uses the name `scratch` as an address (on the host
+// it is only a stand-in for the symbol): the device address comes from
+// hipGetSymbolAddress, taken once per device by mppi_create with that device current.
+static __device__ __align__(256) unsigned char scratch[MPPI_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch` per device
+
+// With `device` current: the device address of its static scratch (taken on first use).
+hipError_t static_scratch_address(int device, void** out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// The stored form's scratch carved out of the static array for (K, N) with `waves`
+// rollout waves; the bytes it needs (for the capacity check) in *bytes.
+Scratch carve_static(unsigned char* base, int K, int N, int waves, mppi_diag** diag, size_t* bytes)
+{
+    Scratch sc{};
+    const int ld = (K + 63) & ~63;
+    size_t off = 0;
+    auto take = [&](size_t b) { unsigned char* p = base + off; off += align256(b); return p; };
+    sc.ld = ld;
+    sc.du = reinterpret_cast<float*>(take(sizeof(float) * 4 * (size_t)N * ld));
+    sc.S = reinterpret_cast<float*>(take(sizeof(float) * (size_t)ld));
+    sc.wstat = reinterpret_cast<WaveStat*>(take(sizeof(WaveStat) * (size_t)waves));
+    sc.u_upd = reinterpret_cast<float*>(take(sizeof(float) * 4 * (size_t)N));
+    *diag = reinterpret_cast<mppi_diag*>(take(sizeof(mppi_diag)));
+    *bytes = off;
+    return sc;
+}
+
 constexpr int kEventsPerUpdate = 3;   // before, between and after the two launches
 
 void free_scratch(mppi_ctx* ctx)
@@ -254,42 +317,56 @@ hipEvent_t mppi::take_event(mppi_ctx* ctx)
 
 namespace {
 
+Scratch ctx_scratch(mppi_ctx* ctx)
+{
+    return Scratch{ctx->du, ctx->ld, ctx->S, ctx->wstat, ctx->u_upd, ctx->counters, ctx->part,
+                   ctx->rho_run, ctx->list_idx, ctx->list_s, ctx->list_n};
+}
+
+// Waves of the rollout launch of this shape: one weight-statistics record each.
+int update_waves(int K, const LaunchConfig& cfg)
+{
+    return cfg.pipe ? (K + 63) / 64 * cfg.lanes : rollout_waves(K, cfg);
+}
+
 // The full update in two launches on stream s: the rollouts with the weight
 // statistics (reduced by their last workgroup into dg), then the weighted sum, which
 // applies and advances as `ap` says: over the stored delta_u, one workgroup per step
-// (the rollout launch copies the warm start into ctx->u_upd for it), or, with
-// cfg.fused, over the per-wave partial sums into ctx->u_upd, whose last workgroup
+// (the rollout launch copies the warm start into sc.u_upd for it), or, with
+// cfg.fused, over the per-wave partial sums into sc.u_upd, whose last workgroup
 // applies.  mark(1) is called between the two launches.
 template <typename Mark>
-hipError_t update_core(mppi_ctx* ctx, const RolloutArgs& a, const LaunchConfig& cfg, float lambda,
+hipError_t update_core(const Scratch& sc, RolloutArgs a, const LaunchConfig& cfg, float lambda,
                        const float* u_in, const ApplyArgs& ap, mppi_diag* dg, hipStream_t s,
                        Mark mark)
 {
+    a.du = sc.du;
+    a.ld = sc.ld;
+    a.S = sc.S;
     UpdateTail tail;
     tail.lambda = lambda;
-    tail.stat = ctx->wstat;
-    tail.counter = ctx->counters;
+    tail.stat = sc.wstat;
+    tail.counter = sc.counters;
     tail.diag = dg;
     hipError_t e;
     if (cfg.fused) {
-        tail.part = ctx->part;
-        tail.rho_run = ctx->rho_run;
-        tail.list_idx = ctx->list_idx;
-        tail.list_s = ctx->list_s;
-        tail.list_n = ctx->list_n;
+        tail.part = sc.part;
+        tail.rho_run = sc.rho_run;
+        tail.list_idx = sc.list_idx;
+        tail.list_s = sc.list_s;
+        tail.list_n = sc.list_n;
         e = cfg.pipe ? launch_rollout_pipe(a, cfg, s, &tail) : launch_rollout_fused(a, cfg, tail, s);
         if (e == hipSuccess) e = mark(1);
         if (e == hipSuccess)
-            e = launch_merge_sum(ctx->part, a.N, ctx->list_idx, ctx->list_s, ctx->list_n, u_in,
-                                 ctx->u_upd, dg, ap, ctx->counters + 1, s);
+            e = launch_merge_sum(sc.part, a.N, sc.list_idx, sc.list_s, sc.list_n, u_in, sc.u_upd, dg,
+                                 ap, sc.counters + 1, s);
     } else {
-        tail.u_copy = ctx->u_upd;
+        tail.u_copy = sc.u_upd;
         e = cfg.pipe ? launch_rollout_pipe(a, cfg, s, &tail) : launch_rollout(a, cfg, s, &tail);
         if (e == hipSuccess) e = mark(1);
         if (e == hipSuccess)
-            e = launch_update_sum(ctx->S, ctx->du, a.K, a.N, ctx->ld, lambda, ctx->u_upd, ctx->wstat,
-                                  cfg.pipe ? (a.K + 63) / 64 * cfg.lanes : rollout_waves(a.K, cfg),
-                                  cfg.lanes, dg, ap, s);
+            e = launch_update_sum(sc.S, sc.du, a.K, a.N, sc.ld, lambda, sc.u_upd, sc.wstat,
+                                  update_waves(a.K, cfg), cfg.lanes, dg, ap, s);
     }
     return e;
 }
@@ -358,6 +435,15 @@ mppi_status mppi_create(int device, mppi_ctx** out)
             hipSuccess) {
         delete ctx;
         return MPPI_E_HIP;
+    }
+    // the static scratch of mppi_update_static on this device (once per device); a
+    // failure is kept for that entry point to report
+    void* p = nullptr;
+    const hipError_t e = static_scratch_address(device, &p);
+    ctx->static_scratch = e == hipSuccess ? p : nullptr;
+    if (e != hipSuccess) {
+        ctx->static_scratch_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        (void)hipGetLastError();
     }
     *out = ctx;
     return MPPI_OK;
@@ -451,10 +537,42 @@ mppi_status mppi_update(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh, co
     const LaunchConfig cfg = config_for(ctx, solve->K, solve->N, M);
     const ApplyArgs ap = apply_args(a.mp, x_hat, u_nom, u_apply, solve->N, *solve);
     HIP_TRY(ctx, mark(0));
-    HIP_TRY(ctx, update_core(ctx, a, cfg, solve->lambda, u_nom, ap, dg, s, mark));
+    HIP_TRY(ctx, update_core(ctx_scratch(ctx), a, cfg, solve->lambda, u_nom, ap, dg, s, mark));
     HIP_TRY(ctx, mark(2));
     if (ctx->profiling)
         for (int i = 0; i < kEventsPerUpdate; ++i) ctx->pending.push_back(ev[i]);
+    return MPPI_OK;
+}
+
+mppi_status mppi_update_static(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh,
+                               const mppi_cost* cost, const mppi_solve* solve, const float* x_hat,
+                               const float* x_ref, const mppi_obstacle* obs, int32_t M,
+                               float* u_nom, float* u_apply, mppi_diag* diag)
+{
+    if (!ctx) return MPPI_E_INVALID_ARG;
+    mppi_status st = mppi_validate(veh, cost, solve, M);
+    if (st != MPPI_OK) return fail(ctx, st, "update_static: invalid parameters");
+    if (!x_hat || !x_ref || !u_nom || !u_apply || (M > 0 && !obs))
+        return fail(ctx, MPPI_E_INVALID_ARG, "update_static: null device pointer");
+    if (!ctx->static_scratch)
+        return fail(ctx, MPPI_E_HIP, "update_static: " + ctx->static_scratch_error);
+    LaunchConfig cfg = config_for(ctx, solve->K, solve->N, M);
+    cfg.fused = 0;                                    // the stored form only
+    mppi_diag* own_diag = nullptr;
+    size_t need = 0;
+    const Scratch sc = carve_static(static_cast<unsigned char*>(ctx->static_scratch), solve->K,
+                                    solve->N, update_waves(solve->K, cfg), &own_diag, &need);
+    if (need > (size_t)MPPI_STATIC_SCRATCH_BYTES)
+        return fail(ctx, MPPI_E_CAPACITY, "update_static: " + std::to_string(need) +
+                                              " bytes of scratch needed, the static array holds " +
+                                              std::to_string((size_t)MPPI_STATIC_SCRATCH_BYTES));
+    RolloutArgs a = rollout_args(*veh, *cost, *solve);
+    a.x_hat = x_hat; a.x_ref = x_ref; a.obs = obs; a.M = M; a.u_nom = u_nom;
+    a.states = nullptr;
+    a.obs_tests = nullptr;
+    const ApplyArgs ap = apply_args(a.mp, x_hat, u_nom, u_apply, solve->N, *solve);
+    HIP_TRY(ctx, update_core(sc, a, cfg, solve->lambda, u_nom, ap, diag ? diag : own_diag,
+                             (hipStream_t)stream, [](int) { return hipSuccess; }));
     return MPPI_OK;
 }
 
@@ -524,7 +642,7 @@ mppi_status mppi_autotune(mppi_ctx* ctx, void* stream, const mppi_vehicle* veh, 
     const ApplyArgs ap = apply_args(a.mp, x_hat, ctx->u_tmp, ctx->u_tmp + 4 * (size_t)solve->N,
                                     solve->N, *solve);
     auto core = [&](const LaunchConfig& c) -> hipError_t {
-        return update_core(ctx, a, c, solve->lambda, u_nom, ap, ctx->diag, s,
+        return update_core(ctx_scratch(ctx), a, c, solve->lambda, u_nom, ap, ctx->diag, s,
                            [](int) { return hipSuccess; });
     };
     std::vector<LaunchConfig> cands;

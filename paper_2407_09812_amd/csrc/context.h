@@ -67,6 +67,10 @@ struct mppi_ctx {
     mppi_profile acc{};
     unsigned long long* obs_tests = nullptr;   // device counter while profiling
     mppi::BatchState batch;
+    // device address of mppi_update_static's static scratch on this context's device
+    // (taken by mppi_create), or nullptr with the reason
+    void* static_scratch = nullptr;
+    std::string static_scratch_error;
 };
 
 namespace mppi {
