@@ -63,6 +63,7 @@ def _load():
                                        dp, dp, dp, dp, i32, dp, dp, dp]),
         "orc_philox_many": (None, [i32, up, up, up]),
         "orc_num_threads": (i32, []),
+        "orc_set_num_threads": (None, [i32]),
         "orc_weights": (i32, [i32, dp, f64, dp, dp]),
         "orc_weighted_update": (None, [i32, i32, dp, dp, dp]),
         "orc_advance": (None, [i32, f64, dp, dp]),
@@ -127,6 +128,11 @@ def philox4x32_10(ctr, key):
 def num_threads() -> int:
     """Threads the oracle's per-sample loop uses."""
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int):
+    """Threads of the per-sample loop from now on (OpenMP)."""
+    _load().orc_set_num_threads(int(n))
 
 
 def philox_many(ctr, key):

@@ -570,3 +570,9 @@ int orc_num_threads(void)
 {
     return omp_get_max_threads();
 }
+
+/* Set the threads of the per-sample loop (timing runs: one thread, or all cores). */
+void orc_set_num_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+}
