@@ -381,70 +381,95 @@ __device__ __forceinline__ float group_sum(float v)
 }
 
 // Minimum and maximum over the 64 lanes of the wave (all lanes active), returned in
-// scalar registers: butterflies within each row of 16 (quad permutations, half-row and
-// row mirrors), then the row broadcasts 15 and 31 fold rows into lane 63, which alone
-// is read (rows a broadcast does not write keep stale values that never reach lane
-// 63).  The two butterflies run interleaved so that each fills the other's DPP hazard
-// slots.  A NaN lane enters as +inf for the minimum and -inf for the maximum, so it
-// never displaces the other lanes' values.
+// scalar registers.  The values are mapped to integer keys that order like the floats
+// (the sign flips the magnitude bits), so that each butterfly step within a row of 16
+// (quad permutations, half-row and row mirrors) is one DPP integer min or max; the row
+// broadcasts 15 and 31 then fold the rows into lane 63, which alone is read (rows a
+// broadcast does not write keep values that never reach lane 63).  A NaN lane enters
+// the minimum as -inf and the maximum as +inf: it widens the range of the others and
+// never shrinks it.
 template <int kCtrl, int kRowMask>
 __device__ __forceinline__ float dpp_move(float x)
 {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), kCtrl, kRowMask, 0xF, false));
 }
 
-template <int kCtrl, int kRowMask>
-__device__ __forceinline__ void range_step(float& lo, float& hi)
+__device__ __forceinline__ int order_key(float f)
 {
-    const float a = dpp_move<kCtrl, kRowMask>(lo), b = dpp_move<kCtrl, kRowMask>(hi);
-    lo = a < lo ? a : lo;
-    hi = b > hi ? b : hi;
+    const int b = __float_as_int(f);
+    return b ^ ((b >> 31) & 0x7fffffff);
+}
+__device__ __forceinline__ float from_order_key(int k)
+{
+    return __int_as_float(k ^ ((k >> 31) & 0x7fffffff));
+}
+
+template <int D, int kCtrl, int kRowMask>
+__device__ __forceinline__ void key_range_step(int (&lo)[D], int (&hi)[D])
+{
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = min(lo[d], __builtin_amdgcn_mov_dpp(lo[d], kCtrl, kRowMask, 0xF, true));
+        hi[d] = max(hi[d], __builtin_amdgcn_mov_dpp(hi[d], kCtrl, kRowMask, 0xF, true));
+    }
+}
+
+// Key ranges of D values per lane over each group of G consecutive lanes (G = 8, 16,
+// 32 or 64), in every lane of the group (G = 64: read from lane 63, uniform).
+template <int D, int G>
+__device__ __forceinline__ void key_ranges(const float (&v)[D], int (&lo)[D], int (&hi)[D])
+{
+    static_assert(G == 8 || G == 16 || G == 32 || G == 64, "group of 8, 16, 32 or 64 lanes");
+    const int neg_inf = order_key(-INFINITY), pos_inf = order_key(INFINITY);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const int k = order_key(v[d]);      // NaN keys lie beyond the infinities
+        lo[d] = max(k, neg_inf);
+        hi[d] = min(k, pos_inf);
+    }
+    key_range_step<D, 0xB1, 0xF>(lo, hi);              // quad_perm [1, 0, 3, 2]
+    key_range_step<D, 0x4E, 0xF>(lo, hi);              // quad_perm [2, 3, 0, 1]
+    key_range_step<D, 0x141, 0xF>(lo, hi);             // row_half_mirror: 8 lanes
+    if (G >= 16) key_range_step<D, 0x140, 0xF>(lo, hi);  // row_mirror: 16 lanes
+    if (G >= 32) key_range_step<D, 0x142, 0xA>(lo, hi);  // row_bcast:15 into rows 1 and 3
+    if (G == 64) {
+        key_range_step<D, 0x143, 0xC>(lo, hi);         // row_bcast:31 into rows 2 and 3
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            lo[d] = __builtin_amdgcn_readlane(lo[d], 63);
+            hi[d] = __builtin_amdgcn_readlane(hi[d], 63);
+        }
+    } else if (G == 32) {
+        const bool low = (__lane_id() & 32) == 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int l0 = __builtin_amdgcn_readlane(lo[d], 31), l1 = __builtin_amdgcn_readlane(lo[d], 63);
+            const int h0 = __builtin_amdgcn_readlane(hi[d], 31), h1 = __builtin_amdgcn_readlane(hi[d], 63);
+            lo[d] = low ? l0 : l1;
+            hi[d] = low ? h0 : h1;
+        }
+    }
 }
 
 __device__ __forceinline__ void wave_range(float v, float& lo, float& hi)
 {
-    const bool nan = v != v;
-    float a = nan ? INFINITY : v, b = nan ? -INFINITY : v;
-    range_step<0xB1, 0xF>(a, b);     // quad_perm [1, 0, 3, 2]
-    range_step<0x4E, 0xF>(a, b);     // quad_perm [2, 3, 0, 1]
-    range_step<0x141, 0xF>(a, b);    // row_half_mirror
-    range_step<0x140, 0xF>(a, b);    // row_mirror
-    range_step<0x142, 0xA>(a, b);    // row_bcast:15 into rows 1 and 3
-    range_step<0x143, 0xC>(a, b);    // row_bcast:31 into rows 2 and 3
-    lo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a), 63));
-    hi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b), 63));
+    const float vv[1] = {v};
+    int l[1], h[1];
+    key_ranges<1, 64>(vv, l, h);
+    lo = from_order_key(l[0]);
+    hi = from_order_key(h[0]);
 }
 
 // Minimum and maximum over each group of G consecutive lanes (G = 8, 16, 32 or 64),
-// returned in every lane of the group: the butterflies within a row stop once they
-// span G lanes; for G = 32 the row broadcast 15 folds rows 0 and 2 into rows 1 and 3,
-// which are read back.  NaN lanes are handled as in wave_range.
+// returned in every lane of the group.  NaN lanes are handled as in wave_range.
 template <int G>
 __device__ __forceinline__ void group_range(float v, float& lo, float& hi)
 {
-    static_assert(G == 8 || G == 16 || G == 32 || G == 64, "group of 8, 16, 32 or 64 lanes");
-    if (G == 64) {
-        wave_range(v, lo, hi);
-        return;
-    }
-    const bool nan = v != v;
-    float a = nan ? INFINITY : v, b = nan ? -INFINITY : v;
-    range_step<0xB1, 0xF>(a, b);                     // quad_perm [1, 0, 3, 2]
-    range_step<0x4E, 0xF>(a, b);                     // quad_perm [2, 3, 0, 1]
-    range_step<0x141, 0xF>(a, b);                    // row_half_mirror: 8 lanes
-    if (G >= 16) range_step<0x140, 0xF>(a, b);       // row_mirror: 16 lanes
-    if (G == 32) {
-        range_step<0x142, 0xA>(a, b);                // row_bcast:15 into rows 1 and 3
-        const bool low = (__lane_id() & 32) == 0;
-        const float a0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a), 31));
-        const float a1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a), 63));
-        const float b0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b), 31));
-        const float b1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b), 63));
-        a = low ? a0 : a1;
-        b = low ? b0 : b1;
-    }
-    lo = a;
-    hi = b;
+    const float vv[1] = {v};
+    int l[1], h[1];
+    key_ranges<1, G>(vv, l, h);
+    lo = from_order_key(l[0]);
+    hi = from_order_key(h[0]);
 }
 
 // Obstacles in LDS, one block per workgroup (see stage_obstacles):
@@ -576,14 +601,182 @@ __device__ __forceinline__ float obstacle_tests(const CostParams& C, float px, f
     return fmaf(C.w_obs, pen, hit > 0.0f ? C.c_col : 0.0f);
 }
 
+// The box of the wave's positions (all lanes active), in scalar registers: the three
+// ranges of wave_range, interleaved (a NaN coordinate widens the box, never shrinks it).
+struct WaveBox {
+    float xlo, xhi, ylo, yhi, zlo, zhi;
+};
+
+__device__ __forceinline__ WaveBox wave_box(float px, float py, float pz)
+{
+    const float v[3] = {px, py, pz};
+    int lo[3], hi[3];
+    key_ranges<3, 64>(v, lo, hi);
+    return WaveBox{from_order_key(lo[0]), from_order_key(hi[0]), from_order_key(lo[1]),
+                   from_order_key(hi[1]), from_order_key(lo[2]), from_order_key(hi[2])};
+}
+
+// Culling by the wave's box of positions.  Among obstacles [i0, i1) only those whose
+// centre lies within R (the block's R_max + slack) of the box can reach a lane: the
+// distance to a vertical cylinder is at least |dx| and |dy|, to a sphere at least |dx|,
+// |dy| and |dz|, so every other obstacle is farther than its r + margin from every lane
+// and adds exactly zero to the penalty and to the hit.  The near obstacles are found 64
+// at a time, one per lane (near_block), then tested in increasing index order, the
+// c-th of a block by lane c mod L of each sample (the L lanes of a sample divide its
+// tests), with S register slots as in obstacle_tests: a slot is scored, then refilled
+// with the candidate S rounds further on (near_tests).  Lanes left without a candidate
+// test the padding entry at index M, which adds zero.  With L = 1 the penalty is summed
+// in the order of obstacle_tests over the same window, term for term (the skipped
+// obstacles add nothing there either).
+struct NearLimits {
+    float xl, xh, yl, yh, zl, zh;
+};
+
+__device__ __forceinline__ NearLimits near_limits(const WaveBox& bx, float R)
+{
+    return NearLimits{bx.xlo - R, bx.xhi + R, bx.ylo - R, bx.yhi + R, bx.zlo - R, bx.zhi + R};
+}
+
+// One block of 64 obstacles [base, min(base + 64, i1)): lane l's obstacle base + l, whose
+// centre c the caller has loaded (o[2 min(base + l, ...)]; any entry past i1).  m: the
+// near ones (bit l), cnt of them; with L > 1 a forward permute (ds_permute, no memory)
+// also sends the index of the c-th near obstacle to lane c (the others send the padding
+// index M to the lanes after the last candidate).
+struct NearBlock {
+    uint64_t m;
+    int cnt, base, cand;
+};
+
+template <int L>
+__device__ __forceinline__ NearBlock near_block(const float4 c, int base, int i1, int M,
+                                                const NearLimits& lim)
+{
+    const int lane = __lane_id(), i = base + lane;
+    const bool near = i < i1 && c.x >= lim.xl && c.x <= lim.xh && c.y >= lim.yl &&
+                      c.y <= lim.yh && (c.w == 0.0f || (c.z >= lim.zl && c.z <= lim.zh));
+    NearBlock nb;
+    nb.m = __ballot(near);
+    nb.cnt = __popcll(nb.m);
+    nb.base = base;
+    nb.cand = M;
+    if (L > 1) {
+        const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(nb.m >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)nb.m, 0u));
+        const int dst = near ? below : nb.cnt + (lane - below);   // a permutation of the lanes
+        nb.cand = __builtin_amdgcn_ds_permute(dst << 2, near ? i : M);
+    }
+    return nb;
+}
+
+// The near obstacles of block nb tested at this lane's position (lane q of its sample),
+// accumulated into the slots' hit flags and the penalty.
+template <int L, int U>
+__device__ __forceinline__ void near_tests(const float4* __restrict__ o, NearBlock nb, int M, int q,
+                                           float px, float py, float pz,
+                                           float (&hits)[U < 2 ? 2 : U], float& pen)
+{
+    constexpr int S = U < 2 ? 2 : U;
+    // the candidate of the next round for this lane: with L = 1 the lowest bit left in
+    // the (uniform) mask; else lane L t + q of the permuted indices
+    int round = 0;
+    auto next = [&]() {
+        int sel = M;
+        if (L == 1) {
+            if (nb.m != 0) {
+                sel = nb.base + __builtin_ctzll(nb.m);
+                nb.m &= nb.m - 1;
+            }
+        } else {
+            const int src = L * round + q;
+            const int v = __builtin_amdgcn_ds_bpermute(src << 2, nb.cand);
+            sel = src < nb.cnt ? v : M;
+        }
+        ++round;
+        return sel;
+    };
+    float4 a[S], b[S];
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+        const int sr = next();
+        a[r] = o[2 * sr];
+        b[r] = o[2 * sr + 1];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    for (int t = 0; t < nb.cnt; t += L * S) {
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+            const float dx = px - a[r].x, dy = py - a[r].y, dz = (pz - a[r].z) * a[r].w;
+            const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            hits[r] = d2 < b[r].x ? 1.0f : hits[r];
+            if (d2 < b[r].y) {
+                const float gap = b[r].z - __builtin_amdgcn_sqrtf(d2);
+                pen = fmaf(gap, gap, pen);
+            }
+            const int sr = next();
+            a[r] = o[2 * sr];
+            b[r] = o[2 * sr + 1];
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// The obstacle term from the slots' hit flags and this lane's penalty share.
+template <int L, int S>
+__device__ __forceinline__ float near_total(const CostParams& C, const float (&hits)[S], float pen)
+{
+    float hit = hits[0];
+#pragma unroll
+    for (int r = 1; r < S; ++r) hit = hits[r] > 0.0f ? 1.0f : hit;
+    if (L > 1) {
+        pen = group_sum<L>(pen);
+        hit = group_sum<L>(hit);
+    }
+    return fmaf(C.w_obs, pen, hit > 0.0f ? C.c_col : 0.0f);
+}
+
+// Obstacle term of Eq. (22) for this lane's position among the obstacles [i0, i1) near
+// the wave's box bx.
+template <int L, int U>
+__device__ __forceinline__ float obstacle_tests_near(const CostParams& C, float px, float py, float pz,
+                                                     const float4* __restrict__ blk, int i0, int i1,
+                                                     int M, int q, float R, const WaveBox& bx,
+                                                     int& tested)
+{
+    constexpr int S = U < 2 ? 2 : U;
+    const float4* o = blk + kObsHeaderFloat4;
+    const NearLimits lim = near_limits(bx, R);
+    float hits[S], pen = 0.0f;
+#pragma unroll
+    for (int r = 0; r < S; ++r) hits[r] = 0.0f;
+    for (int base = i0; base < i1; base += 64) {          // uniform
+        const int i = base + __lane_id();
+        const NearBlock nb = near_block<L>(o[2 * (i < i1 ? i : M)], base, i1, M, lim);
+        tested += nb.cnt;                  // obstacles each sample of this wave tests
+        near_tests<L, U>(o, nb, M, q, px, py, pz, hits, pen);
+    }
+    return near_total<L, S>(C, hits, pen);
+}
+
+// Obstacle term of Eq. (22) for this lane's position (h: the block's header).  Short
+// lists (M < kCullMin) are tested whole; longer ones through the wave's box of
+// positions: the x-sorted window of the box's x-range when the block is sorted, else the
+// whole list, and within it the obstacles near the box (obstacle_tests_near).
 template <int L, int U>
 __device__ __forceinline__ float obstacle_cost(const CostParams& C, const float4 h, float px, float py,
                                                float pz, const float4* __restrict__ blk, int M, int q,
                                                int& tested)
 {
-    int i0, i1;
-    obstacle_window(h, blk, px, M, i0, i1);
-    return obstacle_tests<L, U>(C, px, py, pz, blk, i0, i1, q, tested);
+    if (M < kCullMin) return obstacle_tests<L, U>(C, px, py, pz, blk, 0, M, q, tested);
+    const WaveBox bx = wave_box(px, py, pz);
+    int i0 = 0, i1 = M;
+    if (h.w != 0.0f) {
+        int v0, v1;
+        obstacle_bins_of(h, blk, bx.xlo, bx.xhi, v0, v1);
+        i0 = __builtin_amdgcn_readfirstlane(v0);
+        i1 = __builtin_amdgcn_readfirstlane(v1);
+    }
+    return obstacle_tests_near<L, U>(C, px, py, pz, blk, i0, i1, M, q, h.z, bx, tested);
 }
 
 // Kahan-compensated accumulation of the rollout cost.

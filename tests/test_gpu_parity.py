@@ -412,10 +412,12 @@ def test_end_to_end_update_when_kappa_small(lib, ctx, orc):
 def test_obstacle_test_counter(lib, ctx):
     """With profiling on, the library counts the obstacle distance tests it performs:
     every (sample, state, obstacle) without culling (M < 16), and no more than that
-    -- here far fewer -- when the wave-range culling is on."""
+    -- here far fewer, but some -- when the culling by the wave's box of positions is
+    on (spheres scattered over the path's first metres, some within reach)."""
+    rng = np.random.default_rng(12)
     for M, dense_only in ((10, True), (200, False)):
-        sc = W.c3_agile(K=1000, N=40)
-        sc.obstacles = sc.obstacles[:M]
+        sc = W.c2_line(K=1000, N=40)
+        sc.obstacles = W.spheres_in_box(rng, M, (-1.0, -4.0, 0.5), (9.0, 4.0, 4.5), 0.2, 0.6)
         P = DeviceProblem(lib, sc)
         lib.mppi_reserve(ctx, P.K, P.N, M)
         lib.mppi_profile_enable(ctx, True)
