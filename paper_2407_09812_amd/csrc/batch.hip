@@ -83,15 +83,25 @@ __global__ __launch_bounds__(64 * kStatParts) void batch_stats_kernel(const Batc
     if (threadIdx.x == 0) write_stat_diag(t, D.lanes, D.diag);
 }
 
+// The first rows of up to kWsumLdsInstances instances are staged in LDS once, so that
+// finding a row's instance (a binary search) costs LDS reads rather than dependent
+// global loads; larger batches search the descriptors themselves.
+constexpr int kWsumLdsInstances = 4096;
+
 __global__ __launch_bounds__(kSumThreads) void batch_wsum_kernel(const BatchHeader* __restrict__ hdr,
                                                                  const InstanceDesc* __restrict__ descs)
 {
+    __shared__ int row0[kWsumLdsInstances];
     const int n_rows = hdr->n_rows, n_inst = hdr->n_inst;
+    const bool staged = n_inst <= kWsumLdsInstances;
+    if (staged)
+        for (int i = threadIdx.x; i < n_inst; i += blockDim.x) row0[i] = descs[i].row0;
+    __syncthreads();
     for (int r = blockIdx.x; r < n_rows; r += gridDim.x) {
         int lo = 0, hi = n_inst - 1;           // last instance whose rows start at or before r
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (descs[mid].row0 <= r) lo = mid; else hi = mid - 1;
+            if ((staged ? row0[mid] : descs[mid].row0) <= r) lo = mid; else hi = mid - 1;
         }
         const InstanceDesc& D = descs[lo];
         update_sum_row(D.S, D.du, D.rp.K, D.rp.ld, D.lambda, D.u_nom, D.u_upd, D.diag, r - D.row0);
