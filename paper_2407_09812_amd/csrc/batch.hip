@@ -7,7 +7,7 @@
 //                          instance's obstacles in LDS, rolls the tile out and writes
 //                          its waves' weight statistics
 //   batch_stats_kernel     eight waves per instance reduce its weight statistics
-//   batch_wsum_kernel      persistent over all instances' delta_u rows
+//   batch_wsum_kernel      persistent over all instances' steps (four delta_u rows each)
 //   batch_apply_kernel     one workgroup per instance applies and advances
 // Every stage calls the same device bodies as the one-instance kernels, so an
 // instance's results are bit-identical alone and inside a batch (for the same
@@ -83,29 +83,31 @@ __global__ __launch_bounds__(64 * kStatParts) void batch_stats_kernel(const Batc
     if (threadIdx.x == 0) write_stat_diag(t, D.lanes, D.diag);
 }
 
-// The first rows of up to kWsumLdsInstances instances are staged in LDS once, so that
-// finding a row's instance (a binary search) costs LDS reads rather than dependent
-// global loads; larger batches search the descriptors themselves.
+// Persistent over every instance's steps (four rows each); the first step of up to
+// kWsumLdsInstances instances is staged in LDS once, so that finding a step's instance (a
+// binary search) costs LDS reads rather than dependent global loads; larger batches
+// search the descriptors themselves.
 constexpr int kWsumLdsInstances = 4096;
 
 __global__ __launch_bounds__(kSumThreads) void batch_wsum_kernel(const BatchHeader* __restrict__ hdr,
                                                                  const InstanceDesc* __restrict__ descs)
 {
-    __shared__ int row0[kWsumLdsInstances];
-    const int n_rows = hdr->n_rows, n_inst = hdr->n_inst;
+    __shared__ int step0[kWsumLdsInstances];
+    const int n_steps = hdr->n_rows >> 2, n_inst = hdr->n_inst;
     const bool staged = n_inst <= kWsumLdsInstances;
     if (staged)
-        for (int i = threadIdx.x; i < n_inst; i += blockDim.x) row0[i] = descs[i].row0;
+        for (int i = threadIdx.x; i < n_inst; i += blockDim.x) step0[i] = descs[i].row0 >> 2;
     __syncthreads();
-    for (int r = blockIdx.x; r < n_rows; r += gridDim.x) {
-        int lo = 0, hi = n_inst - 1;           // last instance whose rows start at or before r
+    for (int st = blockIdx.x; st < n_steps; st += gridDim.x) {
+        int lo = 0, hi = n_inst - 1;           // last instance whose steps start at or before st
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if ((staged ? row0[mid] : descs[mid].row0) <= r) lo = mid; else hi = mid - 1;
+            if ((staged ? step0[mid] : descs[mid].row0 >> 2) <= st) lo = mid; else hi = mid - 1;
         }
         const InstanceDesc& D = descs[lo];
-        update_sum_row(D.S, D.du, D.rp.K, D.rp.ld, D.lambda, D.u_nom, D.u_upd, D.diag, r - D.row0);
-        __syncthreads();                       // the row's LDS partials are reused
+        update_sum_step4(D.S, D.du, D.rp.K, D.rp.ld, D.lambda, D.u_nom, D.u_upd, D.diag,
+                         st - (D.row0 >> 2));
+        __syncthreads();                       // the step's LDS partials are reused
     }
 }
 
@@ -160,7 +162,7 @@ hipError_t launch_batch_tail(BatchHeader* hdr, const InstanceDesc* descs, int n_
 {
     hipLaunchKernelGGL(batch_stats_kernel, dim3(n_cap), dim3(64 * kStatParts), 0, stream, hdr,
                        descs);
-    hipLaunchKernelGGL(batch_wsum_kernel, dim3(cu_count * 8), dim3(kSumThreads), 0, stream, hdr,
+    hipLaunchKernelGGL(batch_wsum_kernel, dim3(cu_count * 4), dim3(kSumThreads), 0, stream, hdr,
                        descs);
     hipLaunchKernelGGL(batch_apply_kernel, dim3(n_cap), dim3(256), 0, stream, hdr, descs);
     return hipGetLastError();

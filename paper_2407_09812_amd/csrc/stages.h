@@ -1134,6 +1134,84 @@ __device__ __forceinline__ void update_sum_row(const float* __restrict__ S, cons
     }
 }
 
+// The four rows of step j (controls d = 0..3) by one workgroup of kSumThreads threads:
+// every thread sums the same samples of each row as update_sum_row's thread of the same
+// index, in the same order, and each row is reduced by the same tree, so the results
+// equal update_sum_row's bit for bit; the weight of each sample is formed once for the
+// four rows and all four rows' loads are in flight together.
+__device__ __forceinline__ void update_sum_step4(const float* __restrict__ S,
+                                                 const float* __restrict__ du, int K, int ld,
+                                                 float lambda, const float* __restrict__ u_in,
+                                                 float* __restrict__ u_out,
+                                                 const mppi_diag* __restrict__ diag, int j)
+{
+    __shared__ float sh[4][kSumThreads / 64];
+    const int tid = threadIdx.x;
+    const float rho = diag->rho, eta = diag->eta;
+    const bool ok = diag->status == MPPI_OK;
+    if (!ok) {
+        if (tid < 4) u_out[4 * j + tid] = u_in[4 * j + tid];
+        return;
+    }
+    const float scale = 1.44269504089f / lambda;
+    const float* src = du + (size_t)(4 * j) * ld;
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    auto wt = [&](float s) { return isfinite(s) ? __builtin_amdgcn_exp2f((rho - s) * scale) : 0.0f; };
+    constexpr int stride = kSumThreads;
+    if ((ld & 3) == 0) {
+        const int K4 = K >> 2;
+        const float4* c4 = reinterpret_cast<const float4*>(S);
+        auto clamp4 = [&](int idx) { return idx < K4 ? idx : K4 - 1; };
+        for (int i = tid; i < K4; i += 4 * stride) {     // four float4 per row in flight
+            float4 c[4], a[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int ic = clamp4(i + u * stride);
+                c[u] = c4[ic];
+#pragma unroll
+                for (int d = 0; d < 4; ++d)
+                    a[d][u] = reinterpret_cast<const float4*>(src + (size_t)d * ld)[ic];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool in = i + u * stride < K4;
+                const float4 cc = in ? c[u] : make_float4(INFINITY, INFINITY, INFINITY, INFINITY);
+                const float4 w = make_float4(wt(cc.x), wt(cc.y), wt(cc.z), wt(cc.w));
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const float4 av = in ? a[d][u] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    acc[d] = fmaf(av.x, w.x, acc[d]);
+                    acc[d] = fmaf(av.y, w.y, acc[d]);
+                    acc[d] = fmaf(av.z, w.z, acc[d]);
+                    acc[d] = fmaf(av.w, w.w, acc[d]);
+                }
+            }
+        }
+        for (int k = 4 * K4 + tid; k < K; k += stride) {
+            const float w = wt(S[k]);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) acc[d] = fmaf(src[(size_t)d * ld + k], w, acc[d]);
+        }
+    } else {
+        for (int k = tid; k < K; k += stride) {
+            const float w = wt(S[k]);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) acc[d] = fmaf(src[(size_t)d * ld + k], w, acc[d]);
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        acc[d] = wave_sum(acc[d]);
+        if ((tid & 63) == 0) sh[d][tid >> 6] = acc[d];
+    }
+    __syncthreads();
+    if (tid < 4) {
+        float t = 0.0f;
+        for (int i = 0; i < kSumThreads / 64; ++i) t += sh[tid][i];
+        u_out[4 * j + tid] = u_in[4 * j + tid] + t / eta;
+    }
+}
+
 // Weighted sums of step j's rows (Eq. (5)), then the apply and advance (Algorithm 1;
 // Sec. IV-B), one workgroup of kSumStepThreads per step j.  With the plain shift
 // (alpha = 1) workgroup j writes knot j - 1 (= step j's update) and the last also the
