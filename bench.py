@@ -4,9 +4,11 @@
 Headline (the default run's top-level value): the batched configuration -- 256
 vehicles with uneven K in {1024, ..., 16384}, N in [50, 200] and 0-200 spheres, one
 batched update of all of them per step (persistent rollout kernel, HIP graph replay,
-launch shape from the library's autotuner), against the same 256 updates issued as
-sequential one-instance launch sequences ("plain").  The driver's --steps / --warmup
-apply to it.  Inputs are resident on the device before the timed region.
+launch shape from the library's autotuner), the steps enqueued back to back (the host
+plans the next batch while one runs), against the same 256 updates issued as
+sequential one-instance launch sequences ("plain"); the latency percentiles come from a
+second pass with one synchronisation per batch.  The driver's --steps / --warmup apply
+to it.  Inputs are resident on the device before the timed region.
 
 The same JSON line carries, each with its own roofline:
   plain.c2_line, plain.c3_agile  single-vehicle closed loops (K = 4096, N = 100,
@@ -18,7 +20,7 @@ The same JSON line carries, each with its own roofline:
                  512 vehicles for 60 s, admitted by memory budget and batched
                  continuously by the library's server, each state estimate predicted
                  over the running median latency
-  serving_capacity  the same server at higher arrival rates, until the device is busy
+  serving_capacity  the same server at higher arrival rates, until it saturates
   cpu_baseline   the FP64 oracle on the host cores on a bounded sample of the batched
                  workload, single-threaded and on all cores, extrapolated
 
@@ -360,15 +362,23 @@ def run_batched(args, steps: int, warmup: int, plain_rounds: int):
     for t in range(warmup):
         lib.mppi_batch_update(ctx, reqs[t], stream=stream)
     torch.cuda.synchronize()
-    lat = []
+    # throughput: the batched updates enqueued back to back (the library plans batch
+    # t + 1 on the host while batch t runs; each waits for the previous one's warm starts
+    # on the stream), one synchronisation at the end
     t_start = time.perf_counter()
+    for t in range(warmup, total):
+        lib.mppi_batch_update(ctx, reqs[t], stream=stream)
+    stream.synchronize()
+    elapsed = time.perf_counter() - t_start
+    batched = steps_per_batch * steps / elapsed
+    # latency: the same batched updates one at a time, from the call to the results on
+    # the device (synchronised)
+    lat = []
     for t in range(warmup, total):
         t0 = time.perf_counter()
         lib.mppi_batch_update(ctx, reqs[t], stream=stream)
         stream.synchronize()
         lat.append((time.perf_counter() - t0) * 1e3)
-    elapsed = time.perf_counter() - t_start
-    batched = steps_per_batch * steps / elapsed
 
     # the rollout kernel's duration: profiled batches (HIP events around the stage)
     lib.mppi_profile_enable(ctx, True)
@@ -604,7 +614,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20, help="timed batched updates (headline)")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="all",
-                    choices=["all", "c1", "c2", "c3", "paper", "c4", "c5"])
+                    choices=["all", "c1", "c2", "c3", "paper", "c4", "c5", "capacity"])
     ap.add_argument("--plain-steps", type=int, default=200,
                     help="closed-loop updates of each single-vehicle leg")
     ap.add_argument("--plain-warmup", type=int, default=20)
@@ -619,7 +629,7 @@ def main():
     ap.add_argument("--serve-delay", type=float, default=-1.0,
                     help="seconds each served state estimate is predicted forward before its "
                          "update; < 0: the server's running median latency (default)")
-    ap.add_argument("--capacity-rates", default="6000,12000,24000,48000",
+    ap.add_argument("--capacity-rates", default="12000,24000,48000,72000,96000",
                     help="arrival rates (req/s) of the serving-capacity leg ('' skips it)")
     ap.add_argument("--capacity-seconds", type=float, default=4.0)
     ap.add_argument("--launch", default="", metavar="BLOCK,LANES,UNROLL,FUSED,PIPE",
@@ -653,6 +663,16 @@ def main():
                        {"roofline": p.pop("roofline"), "plain": p})
         if "cpu_baseline" in p:
             out["cpu_baseline"] = p.pop("cpu_baseline")
+        print(json.dumps(out), flush=True)
+        return
+    if args.config == "capacity":
+        fixed = parse_launch(args.batch_launch)
+        cfg = dict(zip(("block", "lanes", "unroll", "blocks_per_cu"), fixed)) if fixed else None
+        caps = run_capacity(args, cfg)
+        best = max(caps, key=lambda r: r["value"])
+        out = headline(best["value"], best["requests"], 8, best["latency_ms"]["mean"],
+                       f"c5_serve capacity sweep: Poisson arrivals at {args.capacity_rates} req/s, "
+                       f"{args.capacity_seconds:.0f} s each", {"serving_capacity": caps})
         print(json.dumps(out), flush=True)
         return
     if args.config == "c5":
