@@ -91,9 +91,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str, launch) -> dict:
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source, this workload and launch shape."""
+def profile_record(kernel: str, workload: str) -> dict:
+    """The committed rocprofv3 counter record of `kernel` on `workload`
+    (profiles/hbm_traffic.json), if it was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
@@ -101,10 +101,24 @@ def measured_traffic(kernel: str, workload: str, launch) -> dict:
         recs = json.load(fh)
     for rec in recs.get("records", []):
         if (rec.get("kernel") == kernel and rec.get("workload") == workload
-                and rec.get("launch") == launch
                 and rec.get("kernel_source_hash") == kernel_source_hash()):
-            return rec.get("hbm_bytes_per_launch")
+            return rec
     return None
+
+
+def counter_fields(kernel: str, workload: str, duration_s: float) -> dict:
+    """roofline fields from the committed counters: HBM traffic per launch (FETCH_SIZE and
+    WRITE_SIZE scaled by a plain copy) and the FP32 operations the kernel executed
+    (SQ_INSTS_VALU_FLOPS_FP32), as a rate over the duration measured here; null when the
+    kernel has changed since the counters were taken."""
+    rec = profile_record(kernel, workload)
+    if rec is None:
+        return {"traffic": None, "executed": None}
+    flop = rec["valu_flops_fp32_per_launch"]
+    return {"traffic": rec["hbm_bytes_per_launch"],
+            "executed": {"flop_per_launch": flop, "achieved": flop / duration_s / 1e12,
+                         "unit": "TFLOP/s", "frac": flop / duration_s / PEAK_FP32_VECTOR,
+                         "counters_launch": rec["launch"], "source": rec["summary"]}}
 
 
 def percentile(v, q):
@@ -297,7 +311,7 @@ def run_plain(args, config: str, steps: int, warmup: int, launch_text: str = "",
             "flop_count": DENSE_NOTE,
             "obstacle_tests_per_state": tests / (K * (N + 1)),
             "obstacle_tests_fraction_of_dense": tests / max(1, K * (N + 1) * M),
-            "traffic": measured_traffic(kernel, sc.name, launch),
+            **counter_fields(kernel, sc.name, rollout_ms * 1e-3),
         },
         "reduction": ({"kernel": "update_sum_kernel", "bound": "hbm",
                        "achieved": rbytes / (sum_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
@@ -445,7 +459,7 @@ def run_batched(args, steps: int, warmup: int, plain_rounds: int):
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
                      "flop_per_launch": flop, "flop_count": DENSE_NOTE,
                      "obstacle_tests_fraction_of_dense": tests / max(1, dense_tests),
-                     "traffic": measured_traffic("batch_rollout_kernel", workload, cfg)},
+                     **counter_fields("batch_rollout_kernel", workload, rollout_ms * 1e-3)},
         "reduction": {"kernels": "batch_stats_kernel + batch_wsum_kernel + batch_apply_kernel",
                       "bound": "hbm", "bytes_per_launch": rbytes,
                       "achieved": rbytes / (rest_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
