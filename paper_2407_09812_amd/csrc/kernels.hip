@@ -109,7 +109,7 @@ __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
     // The noise role runs one chunk ahead of the rates role: its first chunk is drawn
     // while the other waves stage the obstacles (the staging work is shifted off wave 0).
     stage_obstacles(obs_lds, obs, a.M, phx, phy, phz, a.cp.margin, (int)blockDim.x - 64, [&]() {
-        if (wv == 0) pipe_noise_chunk<!kFused>(a, u_nom, du_out, writer, kk, 0, up, P, lane);
+        if (wv == 0) pipe_noise_chunk<!kFused>(a, u_nom, x_ref, du_out, writer, kk, 0, up, P, lane);
     });
     __syncthreads();
 
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
     const int nph = nch + kO - 1;
     if (wv == 0) {
         for (int ph = 0; ph < nph; ++ph) {
-            if (ph + 1 < nch) pipe_noise_chunk<!kFused>(a, u_nom, du_out, writer, kk, ph + 1, up, P, lane);
+            if (ph + 1 < nch) pipe_noise_chunk<!kFused>(a, u_nom, x_ref, du_out, writer, kk, ph + 1, up, P, lane);
             __syncthreads();
         }
     } else if (wv == 1) {
@@ -149,10 +149,14 @@ __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
     } else if (wv == 3) {
         for (int ph = 0; ph < nph; ++ph) {
             if (ph >= 2 && ph < nch + 2)
-                pipe_translation_chunk<L>(a, x_ref, oh, obs_lds, phx, phy, phz, x, ph - 2, lane, P);
+                pipe_translation_chunk<L>(a, oh, obs_lds, phx, phy, phz, x, ph - 2, lane, P);
             __syncthreads();
         }
     } else {
+        // The obstacle waves share their SIMDs with the role waves (wave w + 4 with wave
+        // w) and are the ones whose chunk takes longest; by default the older role wave
+        // is issued first, so the obstacle waves raise their issue priority.
+        __builtin_amdgcn_s_setprio(1);
         for (int ph = 0; ph < nph; ++ph) {
             if (ph >= kO - 1) pipe_obstacle_chunk<L, U>(a, obs_lds, S, tested, ph - (kO - 1), sb, q, wv - kO, P);
             __syncthreads();

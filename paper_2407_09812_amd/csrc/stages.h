@@ -305,6 +305,7 @@ struct PipeLdsT {
     float4 p[2][C][64];         // p_{j+1} relative to p_hat, tracking cost
     int2 win[2][C][8];          // culling window of p_{j+1} per obstacle wave
     float cu_fwd[2][C][64];     // input cost, forwarded to the obstacle role
+    float4 xr[4][C][4];         // reference rows j + 1 of chunk c in slot c % 4 (13 floats)
 };
 
 template <int C = kPipeChunk>
@@ -313,13 +314,23 @@ __host__ __device__ constexpr size_t pipe_lds_bytes(int M)
     return obstacle_lds_bytes(M) + sizeof(PipeLdsT<C>);
 }
 
-// Noise role: chunk c of sample k (kk: k clamped to K - 1).
+// Noise role: chunk c of sample k (kk: k clamped to K - 1).  It also copies the chunk's
+// reference rows j + 1 into the ring P.xr, one float per lane, for the translation role
+// three phases later: those reads then wait for LDS alone, not for scalar loads from
+// global memory (which return out of order and so make every wait a full one).
 template <bool kStoreDu, int C>
 __device__ __forceinline__ void pipe_noise_chunk(const RolloutParams& a, const float* __restrict__ u_nom,
+                                                 const float* __restrict__ x_ref,
                                                  float* __restrict__ du_out, bool writer, int kk,
                                                  int c, float (&up)[4], PipeLdsT<C>& P, int lane)
 {
     const size_t ld = (size_t)a.ld;
+    const int rs = lane >> 4, re = lane & 15;         // step and element of the ring entry
+    float xr = 0.0f;
+    if (rs < C && re < 13) {
+        const int row = c * C + rs + 1 < a.N ? c * C + rs + 1 : a.N;
+        xr = x_ref[(size_t)13 * row + re];
+    }
     float un[C][4];                                   // the chunk's u_nom rows, loaded
 #pragma unroll                                                 // together (the last clamped)
     for (int s = 0; s < C; ++s) {
@@ -355,6 +366,7 @@ __device__ __forceinline__ void pipe_noise_chunk(const RolloutParams& a, const f
         P.u[c & 1][s][lane] = make_float4(u[0], u[1], u[2], u[3]);
         P.cu[c & 1][s][lane] = cu;
     }
+    if (rs < C) reinterpret_cast<float*>(P.xr[c & 3][rs])[re] = xr;
 }
 
 // Rates role: chunk c (x holds omega and the rotor thrusts): the controller, then
@@ -409,23 +421,27 @@ __device__ __forceinline__ void pipe_attitude_chunk(const RolloutParams& a, Stat
 // group of 64 / L here): the window that wave would take itself; hands p, that cost,
 // the input cost and the windows on to the obstacle role.
 template <int L, int C>
-__device__ __forceinline__ void pipe_translation_chunk(const RolloutParams& a,
-                                                       const float* __restrict__ x_ref,
-                                                       const float4 oh,
+__device__ __forceinline__ void pipe_translation_chunk(const RolloutParams& a, const float4 oh,
                                                        const float4* __restrict__ obs_lds,
                                                        float phx, float phy, float phz, State& x,
                                                        int c, int lane, PipeLdsT<C>& P)
 {
-    float4 h[5];                           // step s's hand-over, loaded during step s - 1
-#pragma unroll
+    float4 h[5], g[4];                     // step s's hand-over and reference row, loaded
+#pragma unroll                             // during step s - 1
     for (int e = 0; e < 5; ++e) h[e] = P.r[c & 1][0][e][lane];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) g[e] = P.xr[c & 3][0][e];
     for (int s = 0; s < C; ++s) {
         const int j = c * C + s;
         if (j >= a.N) break;
         const float4 ax = h[0], ay = h[1], az = h[2], qv = h[3], wv = h[4];
+        const float rf[13] = {g[0].x, g[0].y, g[0].z, g[0].w, g[1].x, g[1].y, g[1].z,
+                              g[1].w, g[2].x, g[2].y, g[2].z, g[2].w, g[3].x};
         if (s + 1 < C) {
 #pragma unroll
             for (int e = 0; e < 5; ++e) h[e] = P.r[c & 1][s + 1][e][lane];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) g[e] = P.xr[c & 3][s + 1][e];
         }
         const StageAccel A{{ax.x, ax.y, ax.z, ax.w}, {ay.x, ay.y, ay.z, ay.w}, {az.x, az.y, az.z, az.w}};
         rk4_translational(a.mp, x, A);
@@ -438,7 +454,6 @@ __device__ __forceinline__ void pipe_translation_chunk(const RolloutParams& a,
             group_range<G>(x.px, lo, hi);
             obstacle_bins_of(oh, obs_lds, lo, hi, v0, v1);
         }
-        const float* rf = x_ref + (size_t)13 * (j + 1);
         const float tr = tracking_cost(a.cp, x, rf[0] - phx, rf[1] - phy, rf[2] - phz, rf);
         P.p[c & 1][s][lane] = make_float4(x.px, x.py, x.pz, tr);
         P.cu_fwd[c & 1][s][lane] = wv.w;
@@ -455,22 +470,25 @@ __device__ __forceinline__ void pipe_obstacle_chunk(const RolloutParams& a,
                                                     KahanSum& S, int& tested, int c, int sb, int q,
                                                     int ow, const PipeLdsT<C>& P)
 {
-    float4 h = P.p[c & 1][0][sb];
-    float cu = P.cu_fwd[c & 1][0][sb];
+    // the chunk's hand-over read together (one wait for all of it; obstacle_tests waits
+    // for every outstanding LDS read before its own)
+    float4 pts[C];
+    float cus[C];
+    int2 wins[C];
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+        pts[s] = P.p[c & 1][s][sb];
+        cus[s] = P.cu_fwd[c & 1][s][sb];
+        wins[s] = P.win[c & 1][s][ow];
+    }
+#pragma unroll
     for (int s = 0; s < C; ++s) {
         const int j = c * C + s;
         if (j >= a.N) break;
-        const float4 pt = h;
-        const float cj = cu;
-        if (s + 1 < C) {
-            h = P.p[c & 1][s + 1][sb];
-            cu = P.cu_fwd[c & 1][s + 1][sb];
-        }
-        const int2 win = P.win[c & 1][s][ow];
-        const float co = obstacle_tests<L, U>(a.cp, pt.x, pt.y, pt.z, obs_lds,
-                                              __builtin_amdgcn_readfirstlane(win.x),
-                                              __builtin_amdgcn_readfirstlane(win.y), q, tested);
-        S.add(cj + (pt.w + co));
+        const float co = obstacle_tests<L, U>(a.cp, pts[s].x, pts[s].y, pts[s].z, obs_lds,
+                                              __builtin_amdgcn_readfirstlane(wins[s].x),
+                                              __builtin_amdgcn_readfirstlane(wins[s].y), q, tested);
+        S.add(cus[s] + (pts[s].w + co));
     }
 }
 
