@@ -352,6 +352,9 @@ mppi_status mppi_batch_update(mppi_ctx *ctx, void *stream, const mppi_request *r
  * fastest as the context's batch shape and return it.  Synchronises the stream. */
 mppi_status mppi_batch_autotune(mppi_ctx *ctx, void *stream, const mppi_request *reqs, int32_t n,
                                 int32_t reps, mppi_batch_config *best);
+/* The context's batch shape; until set or tuned it is {256, 0, 1, 8, 1} (lanes per
+ * instance, the plain obstacle loop, eight persistent workgroups per compute unit, the
+ * graph replayed). */
 mppi_status mppi_batch_get_config(const mppi_ctx *ctx, mppi_batch_config *out);
 mppi_status mppi_batch_set_config(mppi_ctx *ctx, const mppi_batch_config *cfg);
 

@@ -30,7 +30,7 @@ struct BatchState {
     float* u_upd = nullptr;
     hipEvent_t staged = nullptr;     // the last H2D copy out of plan_host has completed
     bool staged_pending = false;
-    BatchLaunch cfg{256, 1, 4, 4};
+    BatchLaunch cfg{256, 0, 1, 8};   // lanes by occupancy, plain obstacle loop, 8 per CU
     bool use_graph = true;
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;

@@ -223,3 +223,10 @@ def test_batch_autotune(lib, ctx):
     assert lib.mppi_batch_get_config(ctx) == best
     batched = run_batch(lib, ctx, insts)
     assert_same(batched, run_alone(lib, ctx, insts, lanes_from=batched))
+
+
+def test_default_batch_shape(lib):
+    """A fresh context's batch shape is the one its header documents."""
+    ctx = lib.Context(0)
+    assert lib.mppi_batch_get_config(ctx) == dict(block=256, lanes=0, unroll=1, blocks_per_cu=8,
+                                                  use_graph=1)
