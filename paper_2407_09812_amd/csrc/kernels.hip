@@ -157,9 +157,20 @@ __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
         // w) and are the ones whose chunk takes longest; by default the older role wave
         // is issued first, so the obstacle waves raise their issue priority.
         __builtin_amdgcn_s_setprio(1);
-        for (int ph = 0; ph < nph; ++ph) {
-            if (ph >= kO - 1) pipe_obstacle_chunk<L, U>(a, obs_lds, S, tested, ph - (kO - 1), sb, q, wv - kO, P);
-            __syncthreads();
+        // a block of vertical cylinders only skips the z terms of the tests
+        const int* bins = reinterpret_cast<const int*>(obs_lds + 1);
+        if (__builtin_amdgcn_readfirstlane(bins[kObsSphereSlot]) == 0) {
+            for (int ph = 0; ph < nph; ++ph) {
+                if (ph >= kO - 1)
+                    pipe_obstacle_chunk<L, U, false>(a, obs_lds, S, tested, ph - (kO - 1), sb, q, wv - kO, P);
+                __syncthreads();
+            }
+        } else {
+            for (int ph = 0; ph < nph; ++ph) {
+                if (ph >= kO - 1)
+                    pipe_obstacle_chunk<L, U, true>(a, obs_lds, S, tested, ph - (kO - 1), sb, q, wv - kO, P);
+                __syncthreads();
+            }
         }
     }
     if (wv >= kO) {

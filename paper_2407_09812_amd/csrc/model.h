@@ -474,7 +474,8 @@ __device__ __forceinline__ void group_range(float v, float& lo, float& hi)
 
 // Obstacles in LDS, one block per workgroup (see stage_obstacles):
 //   float4 header (x0, 1 / bin width, R_max + slack, culling on)
-//   kObsBins + 1 bin starts (int, padded to 68): first obstacle with x >= x0 + b w
+//   kObsBins + 1 bin starts (int, padded to 68): first obstacle with x >= x0 + b w;
+//     int kObsSphereSlot of the padding: 1 if any obstacle is a sphere, else 0
 //   two float4 per obstacle, sorted by x:
 //     a = (cx, cy, cz, zmask)  centre relative to the frame origin; zmask 0 for a
 //                              vertical cylinder (ignore z), 1 for a sphere
@@ -483,6 +484,7 @@ __device__ __forceinline__ void group_range(float v, float& lo, float& hi)
 //   below: obstacle_cost reads up to 2 L max(U, 2) - 1 entries past the last obstacle.
 constexpr int kObsBins = 64;
 constexpr int kObsHeaderFloat4 = 1 + 68 / 4;        // header + padded bin table
+constexpr int kObsSphereSlot = kObsBins + 1;        // bin-table int: any sphere in the block
 constexpr int kObsPad = 64;                         // >= 2 L max(U, 2) - 1, L <= 8, U <= 4
 constexpr int kCullMin = 16, kCullMax = 512;       // sorted and culled for M in this range
 constexpr int kCullKeysInLds = 64;                 // from this M the sort ranks keys in LDS
@@ -547,7 +549,8 @@ __device__ __forceinline__ void obstacle_window(const float4 h, const float4* __
 
 // The tests of obstacles [i0, i1) (uniform over the wave): any window that contains the
 // culling window of every lane in the wave gives the same result.
-template <int L, int U>
+// kZ false: every obstacle of the block is a vertical cylinder (z is not read).
+template <int L, int U, bool kZ = true>
 __device__ __forceinline__ float obstacle_tests(const CostParams& C, float px, float py, float pz,
                                                 const float4* __restrict__ blk, int i0, int i1, int q,
                                                 int& tested)
@@ -576,8 +579,14 @@ __device__ __forceinline__ float obstacle_tests(const CostParams& C, float px, f
     for (int t = 0; t < n; t += R) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const float dx = px - a[r].x, dy = py - a[r].y, dz = (pz - a[r].z) * a[r].w;
-            const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            const float dx = px - a[r].x, dy = py - a[r].y;
+            float d2;
+            if (kZ) {
+                const float dz = (pz - a[r].z) * a[r].w;
+                d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            } else {   // a cylinder's dz is 0 (zmask 0), and fma(dy, dy, 0) rounds as dy * dy
+                d2 = fmaf(dx, dx, dy * dy);
+            }
             hits[r] = d2 < b[r].x ? 1.0f : hits[r];
             if (d2 < b[r].y) {
                 const float gap = b[r].z - __builtin_amdgcn_sqrtf(d2);

@@ -40,7 +40,7 @@ __device__ __forceinline__ void stage_obstacles(float4* blk, const mppi_obstacle
                                                 int M, float phx, float phy, float phz, float margin,
                                                 int tshift = 0, const Hook& hook = Hook())
 {
-    __shared__ unsigned int s_rmax;
+    __shared__ unsigned int s_rmax, s_sph;
     const int t = (int)((threadIdx.x + (unsigned)tshift) % blockDim.x);
     float4* o_lds = blk + kObsHeaderFloat4;
     int* bins = reinterpret_cast<int*>(blk + 1);
@@ -50,13 +50,14 @@ __device__ __forceinline__ void stage_obstacles(float4* blk, const mppi_obstacle
         o_lds[2 * rank] = make_float4(o.c[0] - phx, o.c[1] - phy, o.c[2] - phz,
                                       o.type == MPPI_VCYLINDER ? 0.0f : 1.0f);
         o_lds[2 * rank + 1] = make_float4(o.r * o.r, R * R, R, 0.0f);
+        if (o.type != MPPI_VCYLINDER) s_sph = 1u;
     };
     auto put = [&](int i, int rank) {
         const mppi_obstacle o = obs[i];
         place(o, rank);
         atomicMax(&s_rmax, __float_as_uint(fmaxf(o.r + margin, 0.0f)));
     };
-    if (t == 0) s_rmax = 0u;
+    if (t == 0) { s_rmax = 0u; s_sph = 0u; }
     if (cull && M >= kCullKeysInLds) {
         // long lists: the sort keys (x relative to p_hat) go to LDS first, where the
         // obstacles land afterwards, padded to whole float4 with +inf, and each rank
@@ -153,8 +154,10 @@ __device__ __forceinline__ void stage_obstacles(float4* blk, const mppi_obstacle
             bins[bb] = idx;
         }
     }
-    if (t == 0)
+    if (t == 0) {
         blk[0] = make_float4(x0, 1.0f / w, __uint_as_float(s_rmax) + kCullSlack, cull ? 1.0f : 0.0f);
+        bins[kObsSphereSlot] = (int)s_sph;
+    }
 }
 
 // Running cost of a state against reference row ref (Eqs. (17), (18), (22)); the row's
@@ -464,7 +467,7 @@ __device__ __forceinline__ void pipe_translation_chunk(const RolloutParams& a, c
 // Obstacle role (obstacle wave ow): chunk c for the sample at position sb of the
 // workgroup, lane q of its L lanes: the obstacle term at the handed-over position, and
 // the running cost in the order of rollout_sample, cu + (tracking + obstacle).
-template <int L, int U, int C>
+template <int L, int U, bool kZ, int C>
 __device__ __forceinline__ void pipe_obstacle_chunk(const RolloutParams& a,
                                                     const float4* __restrict__ obs_lds,
                                                     KahanSum& S, int& tested, int c, int sb, int q,
@@ -485,7 +488,7 @@ __device__ __forceinline__ void pipe_obstacle_chunk(const RolloutParams& a,
     for (int s = 0; s < C; ++s) {
         const int j = c * C + s;
         if (j >= a.N) break;
-        const float co = obstacle_tests<L, U>(a.cp, pts[s].x, pts[s].y, pts[s].z, obs_lds,
+        const float co = obstacle_tests<L, U, kZ>(a.cp, pts[s].x, pts[s].y, pts[s].z, obs_lds,
                                               __builtin_amdgcn_readfirstlane(wins[s].x),
                                               __builtin_amdgcn_readfirstlane(wins[s].y), q, tested);
         S.add(cus[s] + (pts[s].w + co));

@@ -104,6 +104,38 @@ def test_pipe_matches_one_wave_kernel(lib, ctx, scene):
             assert e_f <= TOL and e_s <= TOL and f0[3] == a[3] and f1[3] == b[3]
 
 
+@pytest.mark.parametrize("spheres", [0, 1, 100])
+def test_pipe_obstacle_types_match_oracle(lib, ctx, orc, spheres):
+    """The obstacle waves skip the z terms when a block holds vertical cylinders only:
+    the c3 scene with none, one and half of its cylinders turned into spheres, against
+    the oracle, for one and eight obstacle lanes."""
+    sc = W.c3_agile(K=512, N=41)
+    obs = sc.obstacles.copy()
+    # spheres of radius 0.4 on the reference path, centred 0.28 above it: every
+    # sample's cost depends on their z terms (the oracle's costs change everywhere when
+    # they are taken for cylinders)
+    idx = np.random.default_rng(7).choice(len(obs), spheres, replace=False)
+    rows = sc.ref.rows(0, sc.N, sc.dt)
+    at = np.linspace(5, sc.N, spheres).astype(int)
+    obs[idx, 0] = 0.0
+    obs[idx, 1:3] = rows[at, 0:2]
+    obs[idx, 4] = 0.4
+    obs[idx, 3] = rows[at, 2] + 0.7 * obs[idx, 4]
+    sc.obstacles = obs
+    P = DeviceProblem(lib, sc)
+    ks = np.arange(0, P.K, 5)
+    _, du_o, S_o = orc.rollouts_subset(P.o_veh, P.o_cost, P.o_solve, ks, P.o_x_hat, P.o_u_nom,
+                                       P.o_x_ref, P.o_obs, want_states=False)
+    kt = torch.as_tensor(ks, device="cuda")
+    for lanes in (1, 8):
+        du, S = rollout(lib, ctx, P, lanes, 1, 1)
+        du_g = du.view(P.N, 4, P.K)[:, :, kt].permute(2, 0, 1).double().cpu().numpy()
+        e_du = rel_err(du_g, du_o, np.asarray(sc.sigma)).max()
+        e_S, flips = check_cost_flips(S[kt].double().cpu().numpy(), S_o, sc.cost["obs_collision"], TOL)
+        print(f"spheres {spheres} lanes {lanes}: du {e_du:.2e} S {e_S:.2e} flips {flips}")
+        assert e_du <= TOL and e_S <= TOL and flips <= 2
+
+
 def test_pipe_rollouts_match_oracle(lib, ctx, orc):
     sc = W.c3_agile(K=512, N=41)
     P = DeviceProblem(lib, sc)
