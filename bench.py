@@ -4,7 +4,8 @@
 Headline (the default run's top-level value): the batched configuration -- 256
 vehicles with uneven K in {1024, ..., 16384}, N in [50, 200] and 0-200 spheres, one
 batched update of all of them per step (persistent rollout kernel, HIP graph replay,
-launch shape from the library's autotuner), the steps enqueued back to back (the host
+the library's default launch shapes, which its autotuners pick for these workloads;
+--autotune runs them), the steps enqueued back to back (the host
 plans the next batch while one runs), against the same 256 updates issued as
 sequential one-instance launch sequences ("plain"); the latency percentiles come from a
 second pass with one synchronisation per batch.  The driver's --steps / --warmup apply
@@ -647,11 +648,13 @@ def main():
                     help="arrival rates (req/s) of the serving-capacity leg ('' skips it)")
     ap.add_argument("--capacity-seconds", type=float, default=4.0)
     ap.add_argument("--launch", default="", metavar="BLOCK,LANES,UNROLL,FUSED,PIPE",
-                    help="fixed launch shape of a single-vehicle --config instead of autotuning")
+                    help="fixed launch shape of a single-vehicle --config")
     ap.add_argument("--batch-launch", default="", metavar="BLOCK,LANES,UNROLL,BLOCKS_PER_CU",
-                    help="fixed batched launch shape instead of autotuning")
-    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
-                    help="use the library's default launch shapes")
+                    help="fixed batched launch shape")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the launch shapes first (mppi_autotune, mppi_batch_autotune) "
+                         "instead of the library's defaults; the committed profiles are taken "
+                         "at the default shapes")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="oracle CPU-baseline budget per timed mode (0 skips it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
