@@ -4,7 +4,10 @@ the applied control, the advanced warm start and the diagnostics equal mppi_upda
 the same launch shape bit for bit, on consecutive calls whose second is smaller than the
 first (the array keeps the last call's contents), in the wave-specialised and the
 one-wave shape, with and without a caller diag; a stored single-pass shape runs as the
-stored form; an update larger than the array is rejected before any launch."""
+stored form; an update larger than the array is rejected before any launch; and, for
+the callers under graph capture it is for, the update recorded once into a HIP graph
+and replayed three times (eager device work and synchronisations between the replays)
+equals the same three updates issued eagerly, bit for bit, at every replay."""
 import numpy as np
 import pytest
 import torch
@@ -86,5 +89,43 @@ def test_static_update_rejects_what_does_not_fit():
                                    P.u_nom.clone(), torch.empty(8, device="cuda"))
         assert e.value.status == -8
         assert "static array" in str(e.value)
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("shape", [(64, 2, 1, 0, 1), (256, 4, 1, 0, 0)])
+def test_static_update_replays_in_a_graph(shape):
+    import paper_2407_09812_amd as lib
+    ctx = lib.Context(0)
+    try:
+        sc = W.c2_line(K=1024, N=40)
+        P = DeviceProblem(lib, sc, t=1)
+        lib.mppi_set_config(ctx, P.K, P.N, P.M, *shape)
+        want = []
+        un, ua, dg = P.u_nom.clone(), torch.full((8,), float("nan"), device="cuda"), lib.new_diag()
+        for _ in range(3):
+            lib.mppi_update_static(ctx, sc.veh, sc.cost, P.solve, P.x_hat, P.x_ref, P.obs, P.M, un,
+                                   ua, dg)
+            torch.cuda.synchronize()
+            want.append((un.clone(), ua.clone(), dg.clone()))
+
+        un, ua, dg = P.u_nom.clone(), torch.full((8,), float("nan"), device="cuda"), lib.new_diag()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):                      # recorded, not run
+            lib.mppi_update_static(ctx, sc.veh, sc.cost, P.solve, P.x_hat, P.x_ref, P.obs, P.M, un,
+                                   ua, dg)
+        torch.cuda.synchronize()
+        assert torch.equal(un, P.u_nom)                # capture ran nothing
+        for r in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            junk = torch.randn(4096, device="cuda").cumsum(0)   # eager work between replays
+            torch.cuda.synchronize()
+            del junk
+            assert torch.equal(un, want[r][0]), r
+            assert torch.equal(ua, want[r][1]), r
+            assert torch.equal(dg, want[r][2]), r
+        del g
     finally:
         ctx.close()
