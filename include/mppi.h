@@ -282,9 +282,10 @@ typedef struct mppi_launch_config {
 
 /* The shape mppi_update / mppi_rollout use for (K, N, M): a stored entry for the
  * size class (powers of two of K, N and M), else a heuristic: the wave-specialised
- * rollouts (pipe = 1, stored form) with 1, 2, 4 or 8 lanes for M < 16, < 64, < 128 or
- * more, and beyond the pipe's obstacle limit the one-wave kernel aiming at one wave per
- * SIMD.  Host-only. */
+ * rollouts (pipe = 1, stored form) with 1, 2 or 4 lanes for M < 16, < 64 or more (with
+ * 4 or 8 lanes the obstacle waves cull by the box of each chunk of steps), and beyond
+ * the pipe's obstacle limit the one-wave kernel aiming at one wave per SIMD.
+ * Host-only. */
 mppi_status mppi_get_config(const mppi_ctx *ctx, int32_t K, int32_t N, int32_t M,
                             mppi_launch_config *out);
 /* Store a shape for the size class of (K, N, M).  MPPI_E_INVALID_ARG for a shape

@@ -272,7 +272,7 @@ LaunchConfig heuristic_config(int K, int M)
     LaunchConfig c;
     if (M <= kPipeMaxM) {
         c.block = 64;
-        c.lanes = M < 16 ? 1 : M < 64 ? 2 : M < 128 ? 4 : 8;
+        c.lanes = M < 16 ? 1 : M < 64 ? 2 : 4;     // 4: the obstacle waves cull by chunk
         c.unroll = 1;
         c.pipe = 1;
         return c;

@@ -131,6 +131,9 @@ __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
     // loop (the barrier counts waves, not code locations), so that only the role's own
     // parameters are live in its loop.
     const int nph = nch + kO - 1;
+    // with 4 or 8 lanes per sample and a list worth culling, the obstacle waves cull by
+    // the box of each chunk's positions and the translation role takes no windows
+    const bool boxed = L >= 4 && a.M >= kCullMin;
     if (wv == 0) {
         for (int ph = 0; ph < nph; ++ph) {
             if (ph + 1 < nch) pipe_noise_chunk<!kFused>(a, u_nom, x_ref, du_out, writer, kk, ph + 1, up, P, lane);
@@ -149,7 +152,7 @@ __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
     } else if (wv == 3) {
         for (int ph = 0; ph < nph; ++ph) {
             if (ph >= 2 && ph < nch + 2)
-                pipe_translation_chunk<L>(a, oh, obs_lds, phx, phy, phz, x, ph - 2, lane, P);
+                pipe_translation_chunk<L>(a, oh, obs_lds, phx, phy, phz, x, ph - 2, lane, P, !boxed);
             __syncthreads();
         }
     } else {
@@ -159,18 +162,26 @@ __global__ __launch_bounds__(64 * (4 + 8)) void rollout_pipe_kernel(
         __builtin_amdgcn_s_setprio(1);
         // a block of vertical cylinders only skips the z terms of the tests
         const int* bins = reinterpret_cast<const int*>(obs_lds + 1);
-        if (__builtin_amdgcn_readfirstlane(bins[kObsSphereSlot]) == 0) {
+        const bool zfree = __builtin_amdgcn_readfirstlane(bins[kObsSphereSlot]) == 0;
+        auto phases = [&](auto chunk) {
             for (int ph = 0; ph < nph; ++ph) {
-                if (ph >= kO - 1)
-                    pipe_obstacle_chunk<L, U, false>(a, obs_lds, S, tested, ph - (kO - 1), sb, q, wv - kO, P);
+                if (ph >= kO - 1) chunk(ph - (kO - 1));
                 __syncthreads();
             }
-        } else {
-            for (int ph = 0; ph < nph; ++ph) {
-                if (ph >= kO - 1)
-                    pipe_obstacle_chunk<L, U, true>(a, obs_lds, S, tested, ph - (kO - 1), sb, q, wv - kO, P);
-                __syncthreads();
+        };
+        if constexpr (L >= 4) {
+            if (boxed) {
+                if (zfree)
+                    phases([&](int cc) { pipe_obstacle_chunk_box<L, U, false>(a, oh, obs_lds, S, tested, cc, sb, q, P); });
+                else
+                    phases([&](int cc) { pipe_obstacle_chunk_box<L, U, true>(a, oh, obs_lds, S, tested, cc, sb, q, P); });
             }
+        }
+        if (!boxed) {
+            if (zfree)
+                phases([&](int cc) { pipe_obstacle_chunk<L, U, false>(a, obs_lds, S, tested, cc, sb, q, wv - kO, P); });
+            else
+                phases([&](int cc) { pipe_obstacle_chunk<L, U, true>(a, obs_lds, S, tested, cc, sb, q, wv - kO, P); });
         }
     }
     if (wv >= kO) {

@@ -414,19 +414,21 @@ __device__ __forceinline__ void key_range_step(int (&lo)[D], int (&hi)[D])
     }
 }
 
-// Key ranges of D values per lane over each group of G consecutive lanes (G = 8, 16,
-// 32 or 64), in every lane of the group (G = 64: read from lane 63, uniform).
+// A lane's key range of value v, merged into (lo, hi): NaN keys lie beyond the
+// infinities, so a NaN widens the range to an infinity and never narrows it.
+__device__ __forceinline__ void key_range_of(float v, int& lo, int& hi)
+{
+    const int k = order_key(v);
+    lo = min(lo, max(k, order_key(-INFINITY)));
+    hi = max(hi, min(k, order_key(INFINITY)));
+}
+
+// The ranges (lo, hi) of each lane merged over each group of G consecutive lanes (G =
+// 8, 16, 32 or 64), in every lane of the group (G = 64: read from lane 63, uniform).
 template <int D, int G>
-__device__ __forceinline__ void key_ranges(const float (&v)[D], int (&lo)[D], int (&hi)[D])
+__device__ __forceinline__ void key_ranges_merge(int (&lo)[D], int (&hi)[D])
 {
     static_assert(G == 8 || G == 16 || G == 32 || G == 64, "group of 8, 16, 32 or 64 lanes");
-    const int neg_inf = order_key(-INFINITY), pos_inf = order_key(INFINITY);
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        const int k = order_key(v[d]);      // NaN keys lie beyond the infinities
-        lo[d] = max(k, neg_inf);
-        hi[d] = min(k, pos_inf);
-    }
     key_range_step<D, 0xB1, 0xF>(lo, hi);              // quad_perm [1, 0, 3, 2]
     key_range_step<D, 0x4E, 0xF>(lo, hi);              // quad_perm [2, 3, 0, 1]
     key_range_step<D, 0x141, 0xF>(lo, hi);             // row_half_mirror: 8 lanes
@@ -449,6 +451,19 @@ __device__ __forceinline__ void key_ranges(const float (&v)[D], int (&lo)[D], in
             hi[d] = low ? h0 : h1;
         }
     }
+}
+
+// Key ranges of D values per lane over each group of G consecutive lanes.
+template <int D, int G>
+__device__ __forceinline__ void key_ranges(const float (&v)[D], int (&lo)[D], int (&hi)[D])
+{
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = order_key(INFINITY) + 1;    // above every key key_range_of keeps
+        hi[d] = order_key(-INFINITY) - 1;
+        key_range_of(v[d], lo[d], hi[d]);
+    }
+    key_ranges_merge<D, G>(lo, hi);
 }
 
 __device__ __forceinline__ void wave_range(float v, float& lo, float& hi)
@@ -728,6 +743,93 @@ __device__ __forceinline__ void near_tests(const float4* __restrict__ o, NearBlo
             __builtin_amdgcn_sched_barrier(0);
         }
     }
+}
+
+// near_tests for the C positions p[0..C) of this lane's sample (the steps of a chunk):
+// each candidate's operands are loaded once and tested at every position; per position
+// the hit flags and the penalty are accumulated as near_tests does for one (kZ false:
+// a block of vertical cylinders only, whose z terms are 0).
+template <int L, int U, bool kZ, int C>
+__device__ __forceinline__ void near_tests_chunk(const float4* __restrict__ o, NearBlock nb, int M,
+                                                 int q, const float4 (&p)[C],
+                                                 float (&hits)[C][U < 2 ? 2 : U], float (&pen)[C])
+{
+    constexpr int S = U < 2 ? 2 : U;
+    int round = 0;
+    auto next = [&]() {
+        int sel = M;
+        if (L == 1) {
+            if (nb.m != 0) {
+                sel = nb.base + __builtin_ctzll(nb.m);
+                nb.m &= nb.m - 1;
+            }
+        } else {
+            const int src = L * round + q;
+            const int v = __builtin_amdgcn_ds_bpermute(src << 2, nb.cand);
+            sel = src < nb.cnt ? v : M;
+        }
+        ++round;
+        return sel;
+    };
+    float4 a[S], b[S];
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+        const int sr = next();
+        a[r] = o[2 * sr];
+        b[r] = o[2 * sr + 1];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    for (int t = 0; t < nb.cnt; t += L * S) {
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+#pragma unroll
+            for (int s = 0; s < C; ++s) {
+                const float dx = p[s].x - a[r].x, dy = p[s].y - a[r].y;
+                float d2;
+                if (kZ) {
+                    const float dz = (p[s].z - a[r].z) * a[r].w;
+                    d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                } else {
+                    d2 = fmaf(dx, dx, dy * dy);
+                }
+                hits[s][r] = d2 < b[r].x ? 1.0f : hits[s][r];
+                if (d2 < b[r].y) {
+                    const float gap = b[r].z - __builtin_amdgcn_sqrtf(d2);
+                    pen[s] = fmaf(gap, gap, pen[s]);
+                }
+            }
+            const int sr = next();
+            a[r] = o[2 * sr];
+            b[r] = o[2 * sr + 1];
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// The box of the wave's positions over the C steps of a chunk (each lane holds its
+// sample's positions p[0..C)), uniform: the ranges of wave_box over all of them; with
+// kZ false (vertical cylinders only) the z range is left infinite.
+template <int C, bool kZ>
+__device__ __forceinline__ WaveBox wave_box_steps(const float4 (&p)[C])
+{
+    constexpr int D = kZ ? 3 : 2;
+    int lo[D], hi[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = order_key(INFINITY) + 1;
+        hi[d] = order_key(-INFINITY) - 1;
+    }
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+        key_range_of(p[s].x, lo[0], hi[0]);
+        key_range_of(p[s].y, lo[1], hi[1]);
+        if (kZ) key_range_of(p[s].z, lo[D - 1], hi[D - 1]);
+    }
+    key_ranges_merge<D, 64>(lo, hi);
+    return WaveBox{from_order_key(lo[0]), from_order_key(hi[0]), from_order_key(lo[1]),
+                   from_order_key(hi[1]), kZ ? from_order_key(lo[D - 1]) : -INFINITY,
+                   kZ ? from_order_key(hi[D - 1]) : INFINITY};
 }
 
 // The obstacle term from the slots' hit flags and this lane's penalty share.

@@ -427,7 +427,7 @@ template <int L, int C>
 __device__ __forceinline__ void pipe_translation_chunk(const RolloutParams& a, const float4 oh,
                                                        const float4* __restrict__ obs_lds,
                                                        float phx, float phy, float phz, State& x,
-                                                       int c, int lane, PipeLdsT<C>& P)
+                                                       int c, int lane, PipeLdsT<C>& P, bool win)
 {
     float4 h[5], g[4];                     // step s's hand-over and reference row, loaded
 #pragma unroll                             // during step s - 1
@@ -452,7 +452,7 @@ __device__ __forceinline__ void pipe_translation_chunk(const RolloutParams& a, c
         x.wx = wv.x; x.wy = wv.y; x.wz = wv.z;
         constexpr int G = 64 / L;
         int v0 = 0, v1 = a.M;              // bin reads in flight during the tracking cost
-        if (oh.w != 0.0f) {
+        if (win && oh.w != 0.0f) {         // (uniform; no window when the obstacle role culls)
             float lo, hi;
             group_range<G>(x.px, lo, hi);
             obstacle_bins_of(oh, obs_lds, lo, hi, v0, v1);
@@ -491,6 +491,58 @@ __device__ __forceinline__ void pipe_obstacle_chunk(const RolloutParams& a,
         const float co = obstacle_tests<L, U, kZ>(a.cp, pts[s].x, pts[s].y, pts[s].z, obs_lds,
                                               __builtin_amdgcn_readfirstlane(wins[s].x),
                                               __builtin_amdgcn_readfirstlane(wins[s].y), q, tested);
+        S.add(cus[s] + (pts[s].w + co));
+    }
+}
+
+// Obstacle role with chunk culling (4 or 8 lanes per sample, at least kCullMin
+// obstacles): the wave takes the box of its samples' positions over the chunk's steps
+// and tests only the obstacles of that box's x-window near the box (the exact culling of
+// obstacle_tests_near), at all the chunk's positions at once, each candidate's operands
+// loaded once; then adds each step's running cost as pipe_obstacle_chunk does.
+template <int L, int U, bool kZ, int C>
+__device__ __forceinline__ void pipe_obstacle_chunk_box(const RolloutParams& a, const float4 oh,
+                                                        const float4* __restrict__ obs_lds,
+                                                        KahanSum& S, int& tested, int c, int sb,
+                                                        int q, const PipeLdsT<C>& P)
+{
+    constexpr int R = U < 2 ? 2 : U;
+    const int nv = a.N - c * C < C ? a.N - c * C : C;       // the chunk's steps (>= 1)
+    float4 pts[C];
+    float cus[C];
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+        const int ss = s < nv ? s : 0;     // past the horizon: a copy of step 0 (unused)
+        pts[s] = P.p[c & 1][ss][sb];
+        cus[s] = P.cu_fwd[c & 1][ss][sb];
+    }
+    const WaveBox bx = wave_box_steps<C, kZ>(pts);
+    int i0 = 0, i1 = a.M;
+    if (oh.w != 0.0f) {
+        int v0, v1;
+        obstacle_bins_of(oh, obs_lds, bx.xlo, bx.xhi, v0, v1);
+        i0 = __builtin_amdgcn_readfirstlane(v0);
+        i1 = __builtin_amdgcn_readfirstlane(v1);
+    }
+    const float4* o = obs_lds + kObsHeaderFloat4;
+    const NearLimits lim = near_limits(bx, oh.z);
+    float hits[C][R], pen[C];
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+        pen[s] = 0.0f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) hits[s][r] = 0.0f;
+    }
+    for (int base = i0; base < i1; base += 64) {              // uniform
+        const int i = base + __lane_id();
+        const NearBlock nb = near_block<L>(o[2 * (i < i1 ? i : a.M)], base, i1, a.M, lim);
+        tested += nv * nb.cnt;
+        near_tests_chunk<L, U, kZ, C>(o, nb, a.M, q, pts, hits, pen);
+    }
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+        if (s >= nv) break;
+        const float co = near_total<L, R>(a.cp, hits[s], pen[s]);
         S.add(cus[s] + (pts[s].w + co));
     }
 }
