@@ -176,6 +176,54 @@ __device__ __forceinline__ float state_cost(const CostParams& C, const State& x,
     return tracking_cost(C, x, r[0] - phx, r[1] - phy, r[2] - phz, r) + co;
 }
 
+// Steps whose obstacle terms the one-wave rollouts take together.
+constexpr int kRolloutChunk = 4;
+
+// The obstacle terms (Eq. (22)) of C states of this lane's sample, p[s] its positions
+// (nv of them valid, the rest copies of the first): the wave's box of all of them, the
+// x-window of that box (a sorted block) or the whole list, and among it the obstacles
+// near the box, each loaded once and tested at every position (near_tests_chunk; a
+// block of vertical cylinders only skips the z terms).  With one lane per sample every
+// state's penalty and hit equal those of obstacle_cost, which culls by one state's box:
+// the extra candidates lie beyond every reach of the state, and the sum runs in the
+// same index order.
+template <int L, int U, int C>
+__device__ __forceinline__ void obstacle_costs_chunk(const CostParams& Cp, const float4 h,
+                                                     const float4* __restrict__ blk, int M, int q,
+                                                     const float4 (&p)[C], int nv, float (&co)[C],
+                                                     int& tested)
+{
+    constexpr int R = U < 2 ? 2 : U;
+    const int* bins = reinterpret_cast<const int*>(blk + 1);
+    const bool zfree = __builtin_amdgcn_readfirstlane(bins[kObsSphereSlot]) == 0;
+    const WaveBox bx = zfree ? wave_box_steps<C, false>(p) : wave_box_steps<C, true>(p);
+    int i0 = 0, i1 = M;
+    if (h.w != 0.0f) {
+        int v0, v1;
+        obstacle_bins_of(h, blk, bx.xlo, bx.xhi, v0, v1);
+        i0 = __builtin_amdgcn_readfirstlane(v0);
+        i1 = __builtin_amdgcn_readfirstlane(v1);
+    }
+    const float4* o = blk + kObsHeaderFloat4;
+    const NearLimits lim = near_limits(bx, h.z);
+    float hits[C][R], pen[C];
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+        pen[s] = 0.0f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) hits[s][r] = 0.0f;
+    }
+    for (int base = i0; base < i1; base += 64) {              // uniform
+        const int i = base + __lane_id();
+        const NearBlock nb = near_block<L>(o[2 * (i < i1 ? i : M)], base, i1, M, lim);
+        tested += nv * nb.cnt;
+        if (zfree) near_tests_chunk<L, U, false, C>(o, nb, M, q, p, hits, pen);
+        else near_tests_chunk<L, U, true, C>(o, nb, M, q, p, hits, pen);
+    }
+#pragma unroll
+    for (int s = 0; s < C; ++s) co[s] = near_total<L, R>(Cp, hits[s], pen[s]);
+}
+
 // Rollout of sample k by lane q of its L lanes.  The L lanes integrate the same
 // sample (identical instructions and operands, hence identical trajectories) and
 // divide its obstacle tests; lane q = 0 of a valid sample writes delta_u [N][4][ld]
@@ -223,7 +271,8 @@ __device__ __forceinline__ float rollout_sample(const RolloutParams& a, const fl
     // step (the values are the same).
     float nz[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     const int grp = (__lane_id() & ~(L - 1)) << 2;        // byte address of lane 0 of the group
-    for (int j = 0; j < a.N; ++j) {
+    // Step j: the perturbed control, its input costs (returned) and the model step.
+    auto step = [&](int j) {
         float du[4], u[4];
         if (L == 1) {
             draw_noise(a.np, (uint32_t)k, (uint32_t)j, du);
@@ -258,17 +307,52 @@ __device__ __forceinline__ float rollout_sample(const RolloutParams& a, const fl
         float Tc[4];
         rate_controller(a.mp, x.wx, x.wy, x.wz, u, Tc);
         rk4_step<kLag>(a.mp, x, Tc);
-
-        const float cx = state_cost<L, U>(a.cp, x, x_ref + (size_t)13 * (j + 1), phx, phy, phz,
-                                          oh, obs_lds, a.M, q, tested);
-        S.add(cu + cx);
-
+        return cu;
+    };
+    auto dump = [&](int j) {
         if (kDump && writer) {
             const float vals[17] = {x.px + phx, x.py + phy, x.pz + phz, x.qw, x.qx, x.qy, x.qz,
                                     x.vx, x.vy, x.vz, x.wx, x.wy, x.wz, x.T0, x.T1, x.T2, x.T3};
             float* st = states + (size_t)17 * (j + 1) * ld + k;
 #pragma unroll
             for (int i = 0; i < 17; ++i) st[(size_t)i * ld] = vals[i];
+        }
+    };
+    if (a.M >= kCullMin) {
+        // Culled lists: the obstacle terms of kRolloutChunk steps at a time, by the box
+        // of the wave's positions over those steps (obstacle_costs_chunk); the running
+        // cost is added step by step as below, cu + (tracking + obstacle).
+        for (int j0 = 0; j0 < a.N; j0 += kRolloutChunk) {
+            const int nv = a.N - j0 < kRolloutChunk ? a.N - j0 : kRolloutChunk;   // uniform
+            float4 pc[kRolloutChunk];      // position and tracking cost of each state
+            float cus[kRolloutChunk];
+#pragma unroll
+            for (int s = 0; s < kRolloutChunk; ++s) {
+                if (s < nv) {
+                    const int j = j0 + s;
+                    cus[s] = step(j);
+                    const float* rf = x_ref + (size_t)13 * (j + 1);
+                    const float tr = tracking_cost(a.cp, x, rf[0] - phx, rf[1] - phy, rf[2] - phz, rf);
+                    pc[s] = make_float4(x.px, x.py, x.pz, tr);
+                    dump(j);
+                } else {
+                    pc[s] = pc[0];         // past the horizon: a copy of the first (unused)
+                    cus[s] = 0.0f;
+                }
+            }
+            float co[kRolloutChunk];
+            obstacle_costs_chunk<L, U>(a.cp, oh, obs_lds, a.M, q, pc, nv, co, tested);
+#pragma unroll
+            for (int s = 0; s < kRolloutChunk; ++s)
+                if (s < nv) S.add(cus[s] + (pc[s].w + co[s]));
+        }
+    } else {
+        for (int j = 0; j < a.N; ++j) {
+            const float cu = step(j);
+            const float cx = state_cost<L, U>(a.cp, x, x_ref + (size_t)13 * (j + 1), phx, phy, phz,
+                                              oh, obs_lds, a.M, q, tested);
+            S.add(cu + cx);
+            dump(j);
         }
     }
     if (writer) S_out[k] = S.s;
