@@ -68,7 +68,8 @@ FLOP_PER_TEST = {0: 11, 1: 9}    # per state and obstacle: sphere, vertical cyli
 DENSE_NOTE = ("algorithmic: the FP64 oracle's operation count (984 per rollout-step, 11 per "
               "sphere and 9 per cylinder test at every state), dense; the kernel skips the "
               "obstacle tests culling proves zero and computes the step in fewer operations, so "
-              "it executes fewer (rocprofv3 FP32 lane-op counters in profiles/)")
+              "it executes fewer (rocprofv3 FP32 lane-op counters in profiles/: 'executed'); "
+              "a frac above 1 is the dense work the culling saves, not a rate the VALU ran at")
 
 
 def rollout_flop(K: int, N: int, obstacle_types) -> float:
