@@ -193,6 +193,29 @@ def test_rollout_edge_shapes(lib, ctx, orc):
         check_rollouts(orc, P, du, S, st, np.arange(K))
 
 
+@pytest.mark.parametrize("N", [5, 6, 7])
+def test_rollout_chunked_culling_mixed_obstacles(lib, ctx, orc, N):
+    """The one-wave rollouts take the obstacle terms four steps at a time by the box of
+    those steps' positions: horizons that end inside a chunk, for every lane count, in a
+    scene of cylinders and spheres on the reference path (centred above it, so that
+    their z terms decide), against the oracle."""
+    sc = W.c3_agile(K=256, N=N)
+    obs = sc.obstacles.copy()
+    rows = sc.ref.rows(0, sc.N, sc.dt)
+    idx = np.random.default_rng(8).choice(len(obs), 30, replace=False)
+    at = np.linspace(1, sc.N, 30).astype(int)
+    obs[idx, 0] = 0.0
+    obs[idx, 1:3] = rows[at, 0:2]
+    obs[idx, 4] = 0.4
+    obs[idx, 3] = rows[at, 2] + 0.7 * obs[idx, 4]
+    sc.obstacles = obs
+    P = DeviceProblem(lib, sc)
+    for lanes in (1, 2, 4, 8):
+        lib.mppi_set_config(ctx, P.K, P.N, P.M, 64, lanes, 1)
+        du, S, st = run_rollout(lib, ctx, P)
+        check_rollouts(orc, P, du, S, st, np.arange(P.K))
+
+
 def test_rollout_longest_horizon(lib, ctx, orc):
     """N = 4096 (41 s of flight): states match at 1e-4 over the first 200 steps (the
     longest configured horizon); over the whole horizon binary32 drift stays below
