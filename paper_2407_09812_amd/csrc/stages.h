@@ -1080,8 +1080,18 @@ struct StatSums {
 // sum_w s_w^2 q_w (binary64, in the fixed part order above; Eq. (4)).  When every part
 // is one batch held by a wave of its own, the records stay in registers between the
 // minimum pass and the sum pass: one memory round trip in all.
+// With pre, the caller has already loaded each wave's batch into r (load_stat_batch at
+// w0 = 64 wave + lane, waves below kStatParts), which requires stat_parts_fit(W): the
+// records can then be loaded before other loads and waited for alone.
 template <int kB>
-__device__ inline StatSums reduce_stat_parts(const WaveStat* __restrict__ stat, int W, float lambda)
+__host__ __device__ constexpr bool stat_parts_fit(int W)
+{
+    return W <= kStatStride * kB;
+}
+
+template <int kB>
+__device__ __forceinline__ StatSums reduce_stat_parts(const WaveStat* __restrict__ stat, int W,
+                                                      float lambda, WaveStat (&r)[kB], bool pre)
 {
     __shared__ float sh_v[kStatParts];
     __shared__ int sh_i[kStatParts], sh_n[kStatParts];
@@ -1090,16 +1100,17 @@ __device__ inline StatSums reduce_stat_parts(const WaveStat* __restrict__ stat, 
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const float scale = 1.44269504089f / lambda;
     const int used = (W + 63) / 64 < kStatParts ? (W + 63) / 64 : kStatParts;   // parts with records
-    const bool keep = W <= kStatStride * kB && used <= nw;
-    WaveStat r[kB];
+    const bool keep = stat_parts_fit<kB>(W) && used <= nw;
+    pre = pre && keep;
+    if (!pre)
 #pragma unroll
-    for (int u = 0; u < kB; ++u) r[u] = WaveStat{INFINITY, 0.0f, 0.0f, 0.0f, -1, 0, 0, 0};
+        for (int u = 0; u < kB; ++u) r[u] = WaveStat{INFINITY, 0.0f, 0.0f, 0.0f, -1, 0, 0, 0};
 
     for (int p = wv; p < kStatParts; p += nw) {
         float mv = INFINITY;
         int mi = INT_MAX, nf = 0;
         for (int w0 = 64 * p + lane; w0 < W; w0 += kStatStride * kB) {
-            load_stat_batch<kB>(stat, W, w0, r);
+            if (!pre) load_stat_batch<kB>(stat, W, w0, r);
 #pragma unroll
             for (int u = 0; u < kB; ++u) {
                 nf += r[u].n;
@@ -1139,6 +1150,14 @@ __device__ inline StatSums reduce_stat_parts(const WaveStat* __restrict__ stat, 
 #pragma unroll
     for (int p = 1; p < kStatParts; ++p) { t.eta += sh_eta[p]; t.q2 += sh_q[p]; }
     return t;
+}
+
+template <int kB>
+__device__ __forceinline__ StatSums reduce_stat_parts(const WaveStat* __restrict__ stat, int W,
+                                                      float lambda)
+{
+    WaveStat r[kB];
+    return reduce_stat_parts<kB>(stat, W, lambda, r, false);
 }
 
 // diag from the reduced statistics (ess = 1 / sum w_k^2 = eta^2 / sum_w s_w^2 q_w).
@@ -1405,6 +1424,12 @@ __device__ __forceinline__ void update_sum_shift_step(const float* __restrict__ 
     // Loads at clamped indices, masked where they are used: no load sits in a branch,
     // so a batch of them is in flight together.
     auto clamp4 = [&](int idx) { return idx < K4 ? idx : K4 - 1; };
+    // the statistics records first (vector loads complete in order: they can be waited
+    // for while the delta_u loads below are still in flight)
+    WaveStat rec[4];
+    const bool pre = stat_parts_fit<4>(W);
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (pre && wv < kStatParts) load_stat_batch<4>(stat, W, 64 * wv + (tid & 63), rec);
     float4 c0[4], a0[2][4];                           // the first iteration's operands
     if (K4 > 0) {
 #pragma unroll
@@ -1420,7 +1445,7 @@ __device__ __forceinline__ void update_sum_shift_step(const float* __restrict__ 
     if (tid == 0)
 #pragma unroll
         for (int r = 0; r < 8; ++r) us[r] = u_src[4 * j + (r < 4 * nr ? r : 0)];
-    const StatSums st = reduce_stat_parts<4>(stat, W, lambda);
+    const StatSums st = reduce_stat_parts<4>(stat, W, lambda, rec, pre);
     if (j == 0 && tid == 0) write_stat_diag(st, lanes, diag);
     const bool ok = st.nf > 0;
     float acc[2] = {0.0f, 0.0f};
